@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the HWENO shallow-water hot path on one MI355X.
+
+Workload (default): the 2D dam break on a 4096 x 4096 grid, 9 FP64 fields (eta, m, w and their
+x- and y-derivatives), reflective walls, a seeded bottom of 4 Gaussian bumps, eta = 10 left of a
+random-phase sinusoidal interface near x = 0.5 and 5 right of it. A step is one SSP-RK3 step:
+three fused stage kernels (right-hand side + derivative limiter + Runge-Kutta combination +
+max-reduction of the next Lax-Friedrichs speeds) and a one-thread prologue (dt). Inputs are
+resident in HBM before the timed region.
+
+value = cell right-hand sides per second over the timed steps (3 per node per step).
+roofline = the fused stage kernel against the FP64 vector peak, with the algorithmic flops per
+node counted by the oracle (right-hand side + limiter) plus the Runge-Kutta combination; its
+duration comes from HIP events around every stage launch inside the timed region.
+cpu_baseline = the oracle (plain C++ FP64, OpenMP over rows) timed on this host on a bounded
+sample: one SSP-RK3 step of the same workload at --cpu-n x --cpu-n nodes.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2D HWENO RHS cell-updates/s FP64 (% roofline); batched & adjoint vs plain"
+PEAK_FP64 = 78.6e12   # FP64 vector FLOP/s (FMA = 2), MI355X
+PEAK_HBM = 8.0e12     # B/s
+RK_FLOPS = (18 + 45 + 45) / 3.0   # per node per stage: U + dt R; (3a + b)/4; (a + 2b)/3, 9 fields
+SPEED_FLOPS = 8                   # |u| + c, |v| + c per node (h, 1/h, 2 products, sqrt, 2 adds)
+STAGE_BYTES = (27 * 8 + 30 * 8 + 30 * 8) / 3.0  # per node: stage 1 reads 12 writes 15; 2, 3 read 21 write 9
+RHS_BYTES = 21 * 8                               # bare right-hand side: read 12, write 9
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("hweno_device.hpp", "swe_hweno.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2208_01260_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per stage launch from the committed rocprofv3 PMC summary, if it was taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_src_sha") != kernel_source_sha() or d.get("workload") != workload:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def flop_counts():
+    """Algorithmic flops per node (right-hand side, limiter), counted by the oracle's
+    operation-counting scalar and stored by tests/golden/make_flop_counts.py."""
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "flop_counts.json")))
+    return d["rhs_flops_per_node"], d["limiter_flops_per_node"]
+
+
+def cpu_baseline(n):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_2208_01260_amd import inputs
+
+    oracle.build()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    pr = inputs.c3_2d(n)
+    p = oracle.params_of(pr)
+    t0 = time.perf_counter()
+    oracle.step(p, pr.state, pr.b, pr.bx, pr.by)
+    dt = time.perf_counter() - t0
+    return {"value": 3.0 * pr.cells / dt, "unit": "cell-RHS/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"one SSP-RK3 step (3 right-hand sides, limiter, update) of the dam-break workload at "
+                      f"{n}x{n} nodes, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096, help="grid nodes per direction")
+    ap.add_argument("--cpu-n", type=int, default=2048, help="oracle sample size (nodes per direction)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "the domain decomposition it would use is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2208_01260_amd import inputs
+    from paper_2208_01260_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_gen = time.perf_counter()
+    pr = inputs.c3_2d(args.n)
+    print(f"[bench] inputs {args.n}x{args.n} generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
+          flush=True)
+    workload = f"2D dam break {args.n}x{args.n}, 9 FP64 fields, reflective walls, seeded Gaussian bottom"
+    cells = pr.cells
+    dev = torch.device("cuda:0")
+    state0 = torch.from_numpy(pr.state).to(dev).contiguous()
+    st = state0.clone()
+    s = Solver.from_problem(pr, device=dev)
+    torch.cuda.synchronize()
+
+    # warm-up (graph path), then the graph path timed for reference
+    s.run(st, nsteps=args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(st, nsteps=args.steps)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(f"[bench] graph replay: {graph_ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # timed region: the same steps with an event pair around every fused stage kernel
+    st.copy_(state0)
+    s.set_timing(True)
+    s.run(st, nsteps=args.warmup)
+    s.set_timing(True)  # reset the totals
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    t_sim, k = s.run(st, nsteps=args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    tim = s.get_timing()
+    stage_ms = sum(tim[f"stage{i}"][0] for i in (1, 2, 3))
+    stage_n = sum(tim[f"stage{i}"][1] for i in (1, 2, 3))
+    assert k == args.steps and stage_n == 3 * args.steps, (k, stage_n)
+    ms_per_step = wall * 1e3 / args.steps
+    value = 3.0 * cells * args.steps / wall
+    print(f"[bench] timed: {ms_per_step:.3f} ms/step (events {ev_ms / args.steps:.3f}), stage kernel "
+          f"{stage_ms / stage_n:.3f} ms/launch", file=sys.stderr, flush=True)
+
+    # the bare right-hand side kernel (the metric's unit), alpha given
+    ax, ay = s.alpha(st)
+    out = torch.empty_like(st)
+    s.set_timing(True)
+    for _ in range(args.steps):
+        s.rhs(st, out, alpha=(ax, ay))
+    tim_r = s.get_timing()
+    rhs_ms = tim_r["rhs"][0] / tim_r["rhs"][1]
+    s.set_timing(False)
+
+    f_rhs, f_lim = flop_counts()
+    f_stage = f_rhs + f_lim + RK_FLOPS + SPEED_FLOPS
+    avg_s = stage_ms / stage_n * 1e-3
+    achieved = f_stage * cells / avg_s
+    traffic = measured_traffic(workload)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64, "traffic": traffic,
+            "kernel": "k_stage<2,*> (fused stage: RHS + limiter + RK update + alpha reduction)",
+            "flops_per_node": f_stage, "algorithmic_bytes_per_node": STAGE_BYTES,
+            "hbm_achieved_GBs": STAGE_BYTES * cells / avg_s / 1e9,
+            "avg_launch_ms": avg_s * 1e3}
+    rhs_kernel = {"avg_launch_ms": rhs_ms, "cell_updates_per_s": cells / (rhs_ms * 1e-3),
+                  "flops_per_node": f_rhs, "tflops": f_rhs * cells / (rhs_ms * 1e-3) / 1e12,
+                  "frac_fp64_peak": f_rhs * cells / (rhs_ms * 1e-3) / PEAK_FP64,
+                  "hbm_GBs": RHS_BYTES * cells / (rhs_ms * 1e-3) / 1e9}
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell-RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload, "nx": args.n, "ny": args.n, "fields": 9, "step": "SSP-RK3 (3 fused stages)",
+                   "sim_time_advanced": t_sim},
+        "roofline": roof,
+        "rhs_kernel": rhs_kernel,
+        "graph_replay_ms_per_step": graph_ms,
+        "cell_steps_per_s": cells * args.steps / wall,
+    }
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    s.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+/*
+ * swe_hweno.h — C ABI of the MI355X (gfx950) solver for the well-balanced fifth-order
+ * finite-difference Hermite WENO scheme for the shallow water equations in pre-balanced form
+ * (Zhao & Zhang, arXiv 2208.01260).
+ *
+ * What the library computes (FP64 throughout):
+ *   - the semi-discrete right-hand side of Sec. 2.1 (1D, eq. (2.8)) and Sec. 3 (2D, eq. (3.8)):
+ *     Lax-Friedrichs split (eq. (2.4)), characteristic-wise nonlinear HWENO reconstruction of the
+ *     original-equation fluxes (eqs. (2.5), (2.7)), linear Hermite derivative fluxes (eq. (2.6)),
+ *     the source split that reuses the flux weights (Step 2), and in 2D the four-point mixed
+ *     terms (eq. (3.7));
+ *   - the HWENO derivative limiter of Sec. 2.2 (eqs. (2.12), (2.13)), dimension by dimension;
+ *   - SSP-RK3 with modified derivatives (eq. (2.11)) at CFL-limited time steps.
+ *
+ * Conventions:
+ *   - All array arguments are DEVICE pointers to contiguous FP64 data unless stated otherwise.
+ *   - Node (i, j) sits at the cell centre (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy).
+ *   - A state is a stack of planes [field][ny][nx], x fastest:
+ *       dim = 1: eta = h + b, m = hu, H = eta_x, M = m_x                            (4 planes, ny = 1)
+ *       dim = 2: eta, m = hu, w = hv, H1 = eta_x, M1 = m_x, W1 = w_x,
+ *                H2 = eta_y, M2 = m_y, W2 = w_y                                      (9 planes)
+ *   - The bottom b and its derivatives bx = b_x, by = b_y are single planes.
+ *   - Readings where the paper is silent: alpha of the Lax-Friedrichs split is global per
+ *     direction and per right-hand-side evaluation (max |u| + sqrt(g h), max |v| + sqrt(g h));
+ *     interface eigenvectors use the arithmetic mean of the two adjacent nodes; the limiter uses
+ *     the node's own state; the right-hand side of each stage takes the unmodified stage
+ *     derivatives; dt = cfl / (alpha_x/dx + alpha_y/dy) from the state at the start of a step.
+ *
+ * Errors: every entry point returns an int status (SWE_OK or a negative code); nothing is
+ * thrown across the ABI. Argument errors are detected on the host before any HIP call.
+ * Device-detected dry (h <= 0) or non-finite states set a sticky flag in the context that
+ * swe_hweno_run and swe_hweno_sync report.
+ *
+ * Streams: every call enqueues on the stream given to swe_hweno_init. swe_hweno_rhs,
+ * swe_hweno_limit and swe_hweno_step (with dt_used == NULL) do not synchronise; the caller's
+ * arrays must stay valid until the stream reaches the enqueued work. Calls on one context
+ * must not overlap from several host threads.
+ */
+#ifndef SWE_HWENO_H
+#define SWE_HWENO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_HWENO_ABI_VERSION 1
+
+enum {
+  SWE_OK = 0,
+  SWE_EINVAL = -1,     /* invalid argument (null pointer, size, parameter out of range) */
+  SWE_ENOMEM = -2,     /* device allocation failed */
+  SWE_EHIP = -3,       /* a HIP runtime call failed */
+  SWE_EDRY = -4,       /* a node with h = eta - b <= 0 was met */
+  SWE_ENONFINITE = -5  /* a non-finite value was met */
+};
+
+enum { SWE_BC_PERIODIC = 0, SWE_BC_REFLECTIVE = 1 };
+
+/* flags */
+enum {
+  SWE_FIXED_DT = 1,     /* every step uses params.fixed_dt instead of the CFL step */
+  SWE_FIXED_ALPHA = 2,  /* every right-hand side uses params.alpha_x / alpha_y */
+  SWE_NO_LIMITER = 4    /* skip the derivative limiter (D^mod = D) */
+};
+
+typedef struct swe_hweno_ctx swe_hweno_ctx; /* opaque, owned by the library */
+
+typedef struct {
+  int dim;                  /* 1 or 2 */
+  int nx, ny;               /* nodes per direction; nx >= 4; ny >= 4 (dim 2) or ny == 1 (dim 1) */
+  double x0, x1, y0, y1;    /* domain; x1 > x0 (and y1 > y0 in 2D) */
+  double g;                 /* gravitational constant, > 0 (the paper uses 9.812, Sec. 4) */
+  double cfl;               /* CFL number, > 0 (the paper uses 0.6, Sec. 4) */
+  double eps;               /* epsilon of the nonlinear weights, > 0 (1e-6, eq. (2.7)) */
+  int bc_x, bc_y;           /* SWE_BC_PERIODIC or SWE_BC_REFLECTIVE (mirror about the wall face) */
+  int flags;                /* SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER */
+  double fixed_dt;          /* > 0 when SWE_FIXED_DT is set */
+  double alpha_x, alpha_y;  /* > 0 when SWE_FIXED_ALPHA is set (alpha_y ignored in 1D) */
+} swe_hweno_params;
+
+/* Create a context: validates params, allocates the stage buffers (about 2.7 states of device
+ * memory in 2D), copies the bottom planes b, bx (and by when dim = 2; pass NULL in 1D) from the
+ * caller's device memory. stream is a hipStream_t (NULL = the null stream). On error *out is
+ * left NULL and nothing is allocated. */
+int swe_hweno_init(const swe_hweno_params* params, const double* b, const double* bx, const double* by,
+                   void* stream, swe_hweno_ctx** out);
+
+/* Right-hand side R(state) of the semi-discrete scheme (eq. (2.8) / (3.8)): rhs has the layout
+ * of state. alpha_x < 0 computes alpha from the state on the device (then alpha_y is ignored);
+ * otherwise the given alpha_x, alpha_y are used. state and rhs must not overlap. */
+int swe_hweno_rhs(swe_hweno_ctx* ctx, const double* state, double* rhs, double alpha_x, double alpha_y);
+
+/* Limited derivatives Lim(state) (Sec. 2.2, eq. (2.13)): dmod receives 2 planes (H, M) in 1D or
+ * 6 planes (H1, M1, W1, H2, M2, W2) in 2D. */
+int swe_hweno_limit(swe_hweno_ctx* ctx, const double* state, double* dmod);
+
+/* Lax-Friedrichs speeds of a state: alpha_host[0] = max |u| + c, alpha_host[1] = max |v| + c
+ * (HOST array of 2). Synchronises the stream. Returns SWE_EDRY / SWE_ENONFINITE if met. */
+int swe_hweno_alpha(swe_hweno_ctx* ctx, const double* state, double* alpha_host);
+
+/* One SSP-RK3 step (eq. (2.11)) of state in place. dt <= 0 takes the CFL step (or fixed_dt with
+ * SWE_FIXED_DT). If dt_used (HOST pointer) is not NULL the call synchronises and stores the dt. */
+int swe_hweno_step(swe_hweno_ctx* ctx, double* state, double dt, double* dt_used);
+
+/* nsteps steps of state in place, replaying a captured per-step HIP graph. With t_end > 0 it
+ * stops at t_end (the last step clipped to it; nsteps <= 0 means "until t_end"); t_out and
+ * steps_out (HOST, nullable) receive the time reached and the steps taken. Synchronises. */
+int swe_hweno_run(swe_hweno_ctx* ctx, double* state, int nsteps, double t_end, double* t_out, int* steps_out);
+
+/* Synchronise the context's stream and report (and clear) a device-detected error. */
+int swe_hweno_sync(swe_hweno_ctx* ctx);
+
+/* Free the context (synchronises its stream first). NULL is a no-op. */
+void swe_hweno_destroy(swe_hweno_ctx* ctx);
+
+/* Static message for a status code. */
+const char* swe_hweno_strerror(int code);
+
+/* SWE_HWENO_ABI_VERSION of the built library. */
+int swe_hweno_abi_version(void);
+
+/* Kernel timing with HIP events on the context's stream. swe_hweno_set_timing(ctx, 1) turns it on
+ * (and resets the totals): swe_hweno_run then launches each step's kernels directly instead of
+ * replaying its graph, with an event pair around every fused stage kernel, and swe_hweno_rhs
+ * brackets its kernel too. swe_hweno_get_timing synchronises and returns, in HOST arrays of 4,
+ * the summed milliseconds and launch counts of [bare right-hand side, stage 1, stage 2, stage 3]. */
+int swe_hweno_set_timing(swe_hweno_ctx* ctx, int on);
+int swe_hweno_get_timing(swe_hweno_ctx* ctx, double* ms, long long* launches);
+
+/* Dimensions of the fused stage kernel's tiles (columns of output per wavefront and rows per
+ * wavefront march); for tests and benchmarks. Host-only, no HIP call. */
+int swe_hweno_tile(int* cols_per_wave, int* rows_per_wave);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWE_HWENO_H */

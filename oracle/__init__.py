@@ -69,6 +69,7 @@ def lib():
             "orc_run_delta_f64": (I, [P, _D, _D, _D, _D, I, Dd, _D, _D, ctypes.POINTER(I)]),
             "orc_run_delta_f128": (I, [P, _D, _D, _D, _D, I, Dd, _D, _D, ctypes.POINTER(I)]),
             "orc_count_rhs": (I, [P, _D, _D, _D, _D, Dd, Dd, ctypes.POINTER(ctypes.c_longlong)]),
+            "orc_count_limit": (I, [P, _D, _D, _D, _D, ctypes.POINTER(ctypes.c_longlong)]),
             "orc_rhs_jvp": (I, [P, _D, _D, _D, _D, _D, _D, _D, _D, Dd, Dd, _D, _D]),
             "orc_hw_candidates": (None, [_D, _D, Dd, _D]),
             "orc_hw_beta": (None, [_D, _D, Dd, _D]),
@@ -207,6 +208,15 @@ def count_rhs(p, state, b, bx, by=None, alpha_x=1.0, alpha_y=1.0):
     b, bx, by = _bottom(p, b, bx, by)
     c = (ctypes.c_longlong * 5)()
     _check(lib().orc_count_rhs(ctypes.byref(p), _p(state), _p(b), _p(bx), _p(by), alpha_x, alpha_y, c))
+    return dict(zip(("add", "mul", "div", "sqrt", "cmp"), list(c)))
+
+
+def count_limit(p, state, b, bx, by=None):
+    """Arithmetic of one limiter evaluation: dict(add, mul, div, sqrt, cmp)."""
+    state = _f64(state)
+    b, bx, by = _bottom(p, b, bx, by)
+    c = (ctypes.c_longlong * 5)()
+    _check(lib().orc_count_limit(ctypes.byref(p), _p(state), _p(b), _p(bx), _p(by), c))
     return dict(zip(("add", "mul", "div", "sqrt", "cmp"), list(c)))
 
 

@@ -269,3 +269,20 @@ void orc_ssprk3_linear(double lam, double mu, double dt, int lim_first, double* 
   ssprk3(U, D, 1, 1, dt, f, lim, lim_first != 0);
 }
 }
+
+extern "C" {
+// Count the arithmetic of one limiter evaluation Lim(S): counts = {add/sub, mul, div, sqrt, cmp}.
+int orc_count_limit(const orc_params* p, const double* state, const double* b, const double* bx, const double* by,
+                    long long* counts) {
+  Scheme<Counted> s;
+  int e = make(p, b, bx, by, s);
+  if (e) return e;
+  const size_t n = nodes(p), N = (size_t)nfields(p) * n;
+  std::vector<Counted> S = to_t<Counted>(state, N), Dm((size_t)s.nd * n);
+  Counted::reset();
+  s.limit(S.data(), S.data() + (size_t)s.nu * n, Dm.data());
+  counts[0] = Counted::n_add; counts[1] = Counted::n_mul; counts[2] = Counted::n_div;
+  counts[3] = Counted::n_sqrt; counts[4] = Counted::n_cmp;
+  return OK;
+}
+}

@@ -1,0 +1,88 @@
+"""ctypes binding of libswe_hweno.so (the C ABI declared in include/swe_hweno.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP kernels. The
+library is loaded from this package directory; if it is missing the import fails loudly (there
+is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe_hweno.so")
+
+OK, EINVAL, ENOMEM, EHIP, EDRY, ENONFINITE = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_REFLECTIVE = 0, 1
+FIXED_DT, FIXED_ALPHA, NO_LIMITER = 1, 2, 4
+ABI_VERSION = 1
+
+# every symbol include/swe_hweno.h declares
+EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alpha", "swe_hweno_step",
+           "swe_hweno_run", "swe_hweno_sync", "swe_hweno_destroy", "swe_hweno_strerror", "swe_hweno_abi_version",
+           "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing")
+
+
+class SweError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})" if where else f"{strerror(code)} ({code})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("g", ctypes.c_double), ("cfl", ctypes.c_double), ("eps", ctypes.c_double),
+        ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("flags", ctypes.c_int),
+        ("fixed_dt", ctypes.c_double), ("alpha_x", ctypes.c_double), ("alpha_y", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, I, D = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER(Params)
+    sig = {
+        "swe_hweno_init": (I, [P, dp, dp, dp, vp, ctypes.POINTER(vp)]),
+        "swe_hweno_rhs": (I, [vp, dp, dp, D, D]),
+        "swe_hweno_limit": (I, [vp, dp, dp]),
+        "swe_hweno_alpha": (I, [vp, dp, ctypes.POINTER(D)]),
+        "swe_hweno_step": (I, [vp, dp, D, ctypes.POINTER(D)]),
+        "swe_hweno_run": (I, [vp, dp, I, D, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "swe_hweno_sync": (I, [vp]),
+        "swe_hweno_destroy": (None, [vp]),
+        "swe_hweno_strerror": (ctypes.c_char_p, [I]),
+        "swe_hweno_abi_version": (I, []),
+        "swe_hweno_tile": (I, [ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "swe_hweno_set_timing": (I, [vp, I]),
+        "swe_hweno_get_timing": (I, [vp, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if L.swe_hweno_abi_version() != ABI_VERSION:
+        raise ImportError("libswe_hweno.so ABI version mismatch; rebuild it")
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().swe_hweno_strerror(int(code)).decode()
+    except ImportError:
+        return f"error {code}"
+
+
+def check(code: int, where: str = ""):
+    if code != OK:
+        raise SweError(code, where)

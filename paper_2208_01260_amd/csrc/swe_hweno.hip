@@ -1,0 +1,797 @@
+// MI355X (gfx950) implementation of the C ABI in include/swe_hweno.h: the right-hand side of the
+// well-balanced fifth-order finite-difference HWENO scheme for the shallow water equations, its
+// derivative limiter and SSP-RK3 stages (Zhao & Zhang, arXiv 2208.01260), FP64.
+//
+// Kernel design (one wavefront per workgroup):
+//   * k_stage is the whole stage of eq. (2.11) in one pass: each lane owns one grid column and
+//     marches up a strip of rows. The y-sweep keeps a four-row window of raw node records in
+//     registers and carries the interface flux of the previous row, so each y-interface is
+//     computed once. The x-sweep exchanges the current row between lanes through LDS: lane l
+//     computes the interface left of its column and reads the right one from lane l+1. A wave
+//     covers 64 columns (2 halo columns each side) and writes the 60 interior ones.
+//   * The same kernel writes the bare right-hand side (MODE_RHS), or fuses the limiter of
+//     Sec. 2.2 at the node, the Runge-Kutta combination and the max-reduction of the next
+//     stage's Lax-Friedrichs speeds (MODE_STAGE0/1/2).
+//   * Boundary nodes are read through an index fold: periodic wrap, or the mirror about the wall
+//     face with each field's parity.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hweno_device.hpp"
+#include "swe_hweno.h"
+
+namespace swe {
+
+constexpr int WAVE = 64;
+constexpr int OUT_COLS = WAVE - 4;  // interior columns written per wave
+constexpr int ROWS = 32;            // rows marched per wave
+
+enum { MODE_RHS = 0, MODE_STAGE0 = 1, MODE_STAGE1 = 2, MODE_STAGE2 = 3 };
+enum { ERR_DRY = 1, ERR_NONFINITE = 2 };
+
+// Device scalars of a context.
+struct DevScal {
+  unsigned long long a_n[2];     // alpha of U^n (bits of positive doubles)
+  unsigned long long a_1[2];     // alpha of U^(1)
+  unsigned long long a_2[2];     // alpha of U^(2)
+  unsigned long long a_next[2];  // alpha of U^(n+1)
+  unsigned long long a_fix[2];   // fixed alpha
+  unsigned long long a_rhs[2];   // alpha used by a bare right-hand side
+  double dt, t, t_end, pad0;
+  int active, steps, err, pad1;
+};
+
+struct KArgs {
+  const double* S;        // state whose right-hand side / stage is computed
+  const double* Sn;       // U^n at the start of the step (stages 1, 2)
+  const double* Dn;       // D^{n,mod} (stages 1, 2)
+  const double* b;
+  const double* bx;
+  const double* by;
+  double* out;            // right-hand side, or the next stage state
+  double* Dn_out;         // stage 0: D^{n,mod}
+  const unsigned long long* a_in;  // Lax-Friedrichs speeds used
+  unsigned long long* a_out;       // max-reduction of the output state's speeds
+  DevScal* sc;
+  int nx, ny, bcx, bcy, limiter;
+  double dx, dy, idx, idy, g, eps;
+};
+
+__device__ __forceinline__ double bits2d(unsigned long long u) { return __longlong_as_double((long long)u); }
+
+// Fold an index into [0, n): periodic wrap or mirror about the wall face (one fold suffices for
+// the stencil halos; indices of halo lanes farther out are clamped, their results are unused).
+__device__ __forceinline__ int fold(int i, int n, int bc, bool& refl) {
+  refl = false;
+  if (i < 0) {
+    if (bc == SWE_BC_PERIODIC) i += n; else { i = -1 - i; refl = true; }
+  } else if (i >= n) {
+    if (bc == SWE_BC_PERIODIC) i -= n; else { i = 2 * n - 1 - i; refl = true; }
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Raw node record at (i, j) in the slots of hweno_device.hpp, ghost values by parity:
+// across an x-wall m, H1, W1, M2, B1 are odd; across a y-wall w, W1, H2, M2, B2 are odd.
+template <int DIM>
+__device__ __forceinline__ void load_rec(const KArgs& a, const double* __restrict__ S, int i, int j, double r[NREC]) {
+  bool rx, ry = false;
+  const int ii = fold(i, a.nx, a.bcx, rx);
+  const int jj = DIM == 2 ? fold(j, a.ny, a.bcy, ry) : 0;
+  const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
+  const size_t q = (size_t)jj * a.nx + ii;
+  if (DIM == 2) {
+#pragma unroll
+    for (int f = 0; f < 9; ++f) r[f] = S[f * n + q];
+    r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = a.by[q];
+  } else {
+    r[S_ETA] = S[q]; r[S_M] = S[n + q]; r[S_W] = 0.0;
+    r[S_H1] = S[2 * n + q]; r[S_M1] = S[3 * n + q]; r[S_W1] = 0.0;
+    r[S_H2] = 0.0; r[S_M2] = 0.0; r[S_W2] = 0.0;
+    r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = 0.0;
+  }
+  if (rx) { r[S_M] = -r[S_M]; r[S_H1] = -r[S_H1]; r[S_W1] = -r[S_W1]; r[S_M2] = -r[S_M2]; r[S_BX] = -r[S_BX]; }
+  if (ry) { r[S_W] = -r[S_W]; r[S_W1] = -r[S_W1]; r[S_H2] = -r[S_H2]; r[S_M2] = -r[S_M2]; r[S_BY] = -r[S_BY]; }
+}
+
+template <int DIR>
+__device__ __forceinline__ void iface(const double* r0, const double* r1, const double* r2, const double* r3,
+                                      double alpha, double h, const KArgs& a, IfO& o) {
+  NodeF A, B, C, D;
+  node_frame<DIR>(r0, a.g, A);
+  node_frame<DIR>(r1, a.g, B);
+  node_frame<DIR>(r2, a.g, C);
+  node_frame<DIR>(r3, a.g, D);
+  interface_flux(A, B, C, D, alpha, h, a.eps, a.g, o);
+}
+
+__device__ __forceinline__ void ifo_to_array(const IfO& o, double* v) {
+  v[0] = o.F0; v[1] = o.F1; v[2] = o.F2; v[3] = o.B0; v[4] = o.B1; v[5] = o.B2; v[6] = o.P0;
+  v[7] = o.P1; v[8] = o.P2; v[9] = o.PB; v[10] = o.M0; v[11] = o.M1; v[12] = o.M2; v[13] = o.MB;
+}
+
+// Add the contribution of one sweep (left/right interfaces l, r, spacing id = 1/dx) to the
+// 9 right-hand-side slots R (2D order eta, m, w, H1, M1, W1, H2, M2, W2). un/ut/dn/dt are the
+// slots of the frame's normal and tangential momentum and derivative triples.
+template <int DIR>
+__device__ __forceinline__ void assemble(const double* l, const double* r, double eta, double H1, double H2,
+                                         double g, double id, double R[9]) {
+  const int un = DIR == 0 ? 1 : 2, ut = DIR == 0 ? 2 : 1;
+  const int dn = DIR == 0 ? 3 : 6, dt = DIR == 0 ? 6 : 3;  // first slot of D_n, D_t
+  const double Hn = DIR == 0 ? H1 : H2, Ht = DIR == 0 ? H2 : H1;
+  const double db0 = r[3] - l[3], db1 = r[4] - l[4], db2 = r[5] - l[5];
+  const double ge = g * eta;
+  R[0] -= ((r[0] - l[0]) + ge * db0) * id;
+  R[un] -= ((r[1] - l[1]) + ge * db1) * id;
+  R[ut] -= ((r[2] - l[2]) + ge * db2) * id;
+  const double gn = g * Hn, gt = g * Ht;
+  R[dn + 0] -= ((r[6] - l[6]) + gn * db0) * id;
+  R[dn + un] -= ((r[7] - l[7]) + gn * db1 + ge * (r[9] - l[9])) * id;
+  R[dn + ut] -= ((r[8] - l[8]) + gn * db2) * id;
+  R[dt + 0] -= ((r[10] - l[10]) + gt * db0) * id;
+  R[dt + un] -= ((r[11] - l[11]) + gt * db1 + ge * (r[13] - l[13])) * id;
+  R[dt + ut] -= ((r[12] - l[12]) + gt * db2) * id;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+// Speeds |u| + c, |v| + c of a node for the next Lax-Friedrichs split; flags dry / non-finite.
+__device__ __forceinline__ void speeds(double e, double m, double w, double b, double g, double& ax, double& ay,
+                                       int& err) {
+  const double h = e - b;
+  if (!(h > 0.0)) { err |= (h == h) ? ERR_DRY : ERR_NONFINITE; return; }
+  const double c = sqrt(g * h), ih = 1.0 / h;
+  const double sx = fabs(m * ih) + c, sy = fabs(w * ih) + c;
+  if (!(sx <= DBL_MAX) || !(sy <= DBL_MAX)) { err |= ERR_NONFINITE; return; }
+  ax = fmax(ax, sx);
+  ay = fmax(ay, sy);
+}
+
+__device__ __forceinline__ void flush_speeds(const KArgs& a, double ax, double ay, int err) {
+  ax = wave_max(ax);
+  ay = wave_max(ay);
+  int e = err;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, WAVE);
+  if (threadIdx.x == 0) {
+    atomicMax(&a.a_out[0], (unsigned long long)__double_as_longlong(ax));
+    atomicMax(&a.a_out[1], (unsigned long long)__double_as_longlong(ay));
+    if (e) atomicOr(&a.sc->err, e);
+  }
+}
+
+// --------------------------------------------------------------------------- the fused stage
+template <int DIM, int MODE>
+__global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
+  if (MODE != MODE_RHS && a.sc->active == 0) return;
+  __shared__ double sx[NREC][WAVE];
+  __shared__ double sf[14][WAVE];
+  const int lane = threadIdx.x;
+  const int c = blockIdx.x * OUT_COLS - 2 + lane;  // this lane's column
+  const int r0 = DIM == 2 ? blockIdx.y * ROWS : 0;
+  const int r1 = DIM == 2 ? min(r0 + ROWS, a.ny) : 1;
+  const bool col_out = lane >= 2 && lane < WAVE - 2 && c < a.nx;
+  const double axl = bits2d(a.a_in[0]), ayl = bits2d(a.a_in[1]);
+  const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
+  const double dt = MODE == MODE_RHS ? 0.0 : a.sc->dt;
+  double amx = 0.0, amy = 0.0;
+  int err = 0;
+
+  // y window: rows r-1, r, r+1, r+2 (2D only) and the flux of interface r-1/2
+  double wm1[NREC], w0[NREC], wp1[NREC], wp2[NREC], nxt[NREC];
+  double yprev[14];
+  if (DIM == 2) {
+    double wm2[NREC];
+    load_rec<DIM>(a, a.S, c, r0 - 2, wm2);
+    load_rec<DIM>(a, a.S, c, r0 - 1, wm1);
+    load_rec<DIM>(a, a.S, c, r0, w0);
+    load_rec<DIM>(a, a.S, c, r0 + 1, wp1);
+    load_rec<DIM>(a, a.S, c, r0 + 2, nxt);
+    IfO o;
+    iface<1>(wm2, wm1, w0, wp1, ayl, a.dy, a, o);
+    ifo_to_array(o, yprev);
+  } else {
+    load_rec<DIM>(a, a.S, c, 0, w0);
+  }
+
+  for (int r = r0; r < r1; ++r) {
+    double R[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = 0.0;
+    double ynew[14];
+    if (DIM == 2) {
+#pragma unroll
+      for (int k = 0; k < NREC; ++k) wp2[k] = nxt[k];
+      if (r + 1 < r1) load_rec<DIM>(a, a.S, c, r + 3, nxt);  // prefetch for the next row
+      IfO o;
+      iface<1>(wm1, w0, wp1, wp2, ayl, a.dy, a, o);
+      ifo_to_array(o, ynew);
+    }
+    // x-sweep of row r: neighbours through LDS
+#pragma unroll
+    for (int k = 0; k < NREC; ++k) sx[k][lane] = w0[k];
+    __syncthreads();
+    const int la = max(lane - 2, 0), lb = max(lane - 1, 0), ld = min(lane + 1, WAVE - 1);
+    double xa[NREC], xb[NREC], xd[NREC];
+#pragma unroll
+    for (int k = 0; k < NREC; ++k) { xa[k] = sx[k][la]; xb[k] = sx[k][lb]; xd[k] = sx[k][ld]; }
+    double xl[14];
+    {
+      IfO o;
+      iface<0>(xa, xb, w0, xd, axl, a.dx, a, o);
+      ifo_to_array(o, xl);
+    }
+#pragma unroll
+    for (int k = 0; k < 14; ++k) sf[k][lane] = xl[k];
+    __syncthreads();
+    double xr[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) xr[k] = sf[k][ld];
+
+    if (col_out) {
+      const double eta = w0[S_ETA], H1 = w0[S_H1], H2 = w0[S_H2];
+      assemble<0>(xl, xr, eta, H1, H2, a.g, a.idx, R);
+      if (DIM == 2) assemble<1>(yprev, ynew, eta, H1, H2, a.g, a.idy, R);
+      const size_t q = (size_t)r * a.nx + c;
+      if (MODE == MODE_RHS) {
+        if (DIM == 2) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) a.out[k * n + q] = R[k];
+        } else {
+          a.out[q] = R[0]; a.out[n + q] = R[1]; a.out[2 * n + q] = R[3]; a.out[3 * n + q] = R[4];
+        }
+      } else {
+        // limited derivatives of this stage's state at the node (Sec. 2.2)
+        double Dm[6];
+        if (a.limiter) {
+          limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], xb[S_ETA], xb[S_M], xb[S_W], xd[S_ETA], xd[S_M],
+                      xd[S_W], xb[S_H1], xb[S_M1], xb[S_W1], xd[S_H1], xd[S_M1], xd[S_W1], a.dx, a.idx, a.eps, a.g,
+                      Dm);
+          if (DIM == 2) {
+            double o3[3];
+            limit_frame(w0[S_ETA], w0[S_W], w0[S_M], w0[S_B], wm1[S_ETA], wm1[S_W], wm1[S_M], wp1[S_ETA],
+                        wp1[S_W], wp1[S_M], wm1[S_H2], wm1[S_W2], wm1[S_M2], wp1[S_H2], wp1[S_W2], wp1[S_M2], a.dy,
+                        a.idy, a.eps, a.g, o3);
+            Dm[3] = o3[0]; Dm[4] = o3[2]; Dm[5] = o3[1];
+          }
+        } else {
+          Dm[0] = w0[S_H1]; Dm[1] = w0[S_M1]; Dm[2] = w0[S_W1];
+          Dm[3] = w0[S_H2]; Dm[4] = w0[S_M2]; Dm[5] = w0[S_W2];
+        }
+        // SSP-RK3 combination (eq. (2.11)), written over a common denominator
+        const int nu = DIM == 2 ? 3 : 2, nd = DIM == 2 ? 6 : 2;
+        const int uslot[3] = {S_ETA, S_M, S_W};
+        const int rd[6] = {3, 4, 5, 6, 7, 8};
+        double Unew[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (k >= nu) break;
+          const double u = w0[uslot[k]] + dt * R[k];
+          double v;
+          if (MODE == MODE_STAGE0) v = u;
+          else if (MODE == MODE_STAGE1) v = (3.0 * a.Sn[k * n + q] + u) * 0.25;
+          else v = (a.Sn[k * n + q] + 2.0 * u) / 3.0;
+          Unew[k] = v;
+          a.out[k * n + q] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          if (k >= nd) break;
+          const double u = Dm[k] + dt * R[rd[k]];
+          double v;
+          if (MODE == MODE_STAGE0) {
+            v = u;
+            a.Dn_out[k * n + q] = Dm[k];
+          } else if (MODE == MODE_STAGE1) {
+            v = (3.0 * a.Dn[k * n + q] + u) * 0.25;
+          } else {
+            v = (a.Dn[k * n + q] + 2.0 * u) / 3.0;
+          }
+          a.out[(nu + k) * n + q] = v;
+        }
+        speeds(Unew[0], Unew[1], DIM == 2 ? Unew[2] : 0.0, w0[S_B], a.g, amx, amy, err);
+      }
+    }
+    if (DIM == 2) {
+#pragma unroll
+      for (int k = 0; k < 14; ++k) yprev[k] = ynew[k];
+#pragma unroll
+      for (int k = 0; k < NREC; ++k) { wm1[k] = w0[k]; w0[k] = wp1[k]; wp1[k] = wp2[k]; }
+    }
+  }
+  if (MODE != MODE_RHS) flush_speeds(a, amx, amy, err);
+}
+
+// --------------------------------------------------------------------------- small kernels
+// Lax-Friedrichs speeds of a state (grid-stride), max-reduced into out[2].
+template <int DIM>
+__global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ S, const double* __restrict__ b, size_t n,
+                                               double g, unsigned long long* out, int* errp) {
+  double ax = 0.0, ay = 0.0;
+  int err = 0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+    speeds(S[q], S[n + q], DIM == 2 ? S[2 * n + q] : 0.0, b[q], g, ax, ay, err);
+  ax = wave_max(ax);
+  ay = wave_max(ay);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, WAVE);
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(ax));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(ay));
+    if (err) atomicOr(errp, err);
+  }
+}
+
+// Set two alpha slots (zero, or given values).
+__global__ void k_set2(unsigned long long* p, unsigned long long v0, unsigned long long v1) {
+  if (threadIdx.x == 0) { p[0] = v0; p[1] = v1; }
+}
+
+// Reset the clock of a run or a single step (the error flag is left alone).
+__global__ void k_clock(DevScal* s, double t_end) {
+  if (threadIdx.x == 0) { s->t = 0.0; s->t_end = t_end; s->dt = 0.0; s->active = 1; s->steps = 0; }
+}
+
+__global__ void k_clear_err(DevScal* s) {
+  if (threadIdx.x == 0) s->err = 0;
+}
+
+// Start of a step: alpha of U^n from the previous step's reduction, the CFL step (or fixed),
+// clipped at t_end; clears the reductions this step fills.
+__global__ void k_prologue(DevScal* s, int dim, int fixed_dt, double fdt, double cfl, double dx, double dy,
+                           int use_tend) {
+  if (threadIdx.x != 0) return;
+  s->a_n[0] = s->a_next[0];
+  s->a_n[1] = s->a_next[1];
+  const double ax = bits2d(s->a_n[0]), ay = bits2d(s->a_n[1]);
+  double dt = fixed_dt ? fdt : (dim == 2 ? cfl / (ax / dx + ay / dy) : cfl / (ax / dx));
+  int active = 1;
+  if (use_tend) {
+    if (!(s->t < s->t_end)) { active = 0; dt = 0.0; }
+    else if (s->t + dt > s->t_end) dt = s->t_end - s->t;
+  }
+  if (!(dt > 0.0) || !(dt <= DBL_MAX)) {
+    if (active) s->err |= ERR_NONFINITE;
+    active = 0;
+  }
+  s->active = active;
+  s->dt = dt;
+  if (active) { s->t += dt; s->steps += 1; }
+  s->a_1[0] = s->a_1[1] = 0ull;
+  s->a_2[0] = s->a_2[1] = 0ull;
+  s->a_next[0] = s->a_next[1] = 0ull;
+}
+
+// Stand-alone limiter: one thread per node, neighbours read directly.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_limit(KArgs a) {
+  const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % a.nx), j = (int)(q / a.nx);
+    double c0[NREC], xm[NREC], xp[NREC];
+    load_rec<DIM>(a, a.S, i, j, c0);
+    load_rec<DIM>(a, a.S, i - 1, j, xm);
+    load_rec<DIM>(a, a.S, i + 1, j, xp);
+    double D[3];
+    limit_frame(c0[S_ETA], c0[S_M], c0[S_W], c0[S_B], xm[S_ETA], xm[S_M], xm[S_W], xp[S_ETA], xp[S_M], xp[S_W],
+                xm[S_H1], xm[S_M1], xm[S_W1], xp[S_H1], xp[S_M1], xp[S_W1], a.dx, a.idx, a.eps, a.g, D);
+    if (DIM == 1) {
+      a.out[q] = D[0];
+      a.out[n + q] = D[1];
+      continue;
+    }
+    a.out[q] = D[0]; a.out[n + q] = D[1]; a.out[2 * n + q] = D[2];
+    double ym[NREC], yp[NREC];
+    load_rec<DIM>(a, a.S, i, j - 1, ym);
+    load_rec<DIM>(a, a.S, i, j + 1, yp);
+    limit_frame(c0[S_ETA], c0[S_W], c0[S_M], c0[S_B], ym[S_ETA], ym[S_W], ym[S_M], yp[S_ETA], yp[S_W], yp[S_M],
+                ym[S_H2], ym[S_W2], ym[S_M2], yp[S_H2], yp[S_W2], yp[S_M2], a.dy, a.idy, a.eps, a.g, D);
+    a.out[3 * n + q] = D[0]; a.out[4 * n + q] = D[2]; a.out[5 * n + q] = D[1];
+  }
+}
+
+}  // namespace swe
+
+// =========================================================================== host runtime
+using namespace swe;
+
+struct swe_hweno_ctx {
+  swe_hweno_params p{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // capture stream for the per-step graphs
+  int nf = 0, nd = 0;
+  size_t n = 0;
+  double *b = nullptr, *bx = nullptr, *by = nullptr;
+  double *S1 = nullptr, *S2 = nullptr, *Dn = nullptr;
+  DevScal* sc = nullptr;
+  hipGraphExec_t g1 = nullptr, g8 = nullptr;
+  const double* g_state = nullptr;
+  int g_tend = 0;
+  // kernel timing: event pairs around stage kernels (slot 0 = bare right-hand side, 1..3 = stages)
+  bool timing = false;
+  struct Pending { hipEvent_t a, b; int slot; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[4] = {0, 0, 0, 0};
+  long long launches[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+bool params_ok(const swe_hweno_params* p) {
+  if (!p) return false;
+  if (p->dim != 1 && p->dim != 2) return false;
+  if (p->nx < 4 || p->nx > (1 << 20)) return false;
+  if (p->dim == 2 && (p->ny < 4 || p->ny > (1 << 20))) return false;
+  if (p->dim == 1 && p->ny != 1) return false;
+  if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 31)) return false;
+  if (!(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0))) return false;
+  if (!(p->g > 0) || !(p->cfl > 0) || !(p->eps > 0)) return false;
+  if (!std::isfinite(p->g) || !std::isfinite(p->cfl) || !std::isfinite(p->eps)) return false;
+  if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return false;
+  if (p->flags & ~(SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER)) return false;
+  if ((p->flags & SWE_FIXED_DT) && !(p->fixed_dt > 0)) return false;
+  if ((p->flags & SWE_FIXED_ALPHA) && (!(p->alpha_x > 0) || (p->dim == 2 && !(p->alpha_y > 0)))) return false;
+  return true;
+}
+
+unsigned long long dbits(double v) {
+  unsigned long long u;
+  std::memcpy(&u, &v, sizeof u);
+  return u;
+}
+
+KArgs base_args(const swe_hweno_ctx* c) {
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.b = c->b; a.bx = c->bx; a.by = c->by;
+  a.sc = c->sc;
+  a.nx = c->p.nx; a.ny = c->p.dim == 2 ? c->p.ny : 1;
+  a.bcx = c->p.bc_x; a.bcy = c->p.bc_y;
+  a.limiter = (c->p.flags & SWE_NO_LIMITER) ? 0 : 1;
+  a.dx = (c->p.x1 - c->p.x0) / c->p.nx;
+  a.dy = c->p.dim == 2 ? (c->p.y1 - c->p.y0) / c->p.ny : 1.0;
+  a.idx = 1.0 / a.dx; a.idy = 1.0 / a.dy;
+  a.g = c->p.g; a.eps = c->p.eps;
+  return a;
+}
+
+dim3 stage_grid(const swe_hweno_ctx* c) {
+  const unsigned gx = (unsigned)((c->p.nx + OUT_COLS - 1) / OUT_COLS);
+  const unsigned gy = c->p.dim == 2 ? (unsigned)((c->p.ny + ROWS - 1) / ROWS) : 1u;
+  return dim3(gx, gy, 1);
+}
+
+template <int MODE> void launch_stage_mode(const swe_hweno_ctx* c, const KArgs& a, hipStream_t s) {
+  if (c->p.dim == 2) hipLaunchKernelGGL((k_stage<2, MODE>), stage_grid(c), dim3(WAVE), 0, s, a);
+  else hipLaunchKernelGGL((k_stage<1, MODE>), stage_grid(c), dim3(WAVE), 0, s, a);
+}
+
+void launch_alpha(const swe_hweno_ctx* c, const double* S, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, s, out, 0ull, 0ull);
+  const size_t blocks = (c->n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+  if (c->p.dim == 2) hipLaunchKernelGGL(k_alpha<2>, dim3(grid), dim3(256), 0, s, S, c->b, c->n, c->p.g, out, &c->sc->err);
+  else hipLaunchKernelGGL(k_alpha<1>, dim3(grid), dim3(256), 0, s, S, c->b, c->n, c->p.g, out, &c->sc->err);
+}
+
+hipEvent_t take_event(swe_hweno_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Start / end an event-timed region on the context stream (no-op unless timing is on).
+int time_begin(swe_hweno_ctx* c, hipStream_t s) {
+  if (!c || !c->timing || s != c->stream) return -1;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return -1;
+  hipEventRecord(a, s);
+  c->pending.push_back({a, b, -1});
+  return (int)c->pending.size() - 1;
+}
+void time_end(swe_hweno_ctx* c, int id, int slot, hipStream_t s) {
+  if (id < 0) return;
+  hipEventRecord(c->pending[id].b, s);
+  c->pending[id].slot = slot;
+}
+
+// Accumulate finished event pairs (the stream must have been synchronised).
+void collect_timing(swe_hweno_ctx* c) {
+  for (const auto& pe : c->pending) {
+    float ms = 0.f;
+    if (pe.slot >= 0 && hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+      c->ms[pe.slot] += ms;
+      c->launches[pe.slot] += 1;
+    }
+    c->pool.push_back(pe.a);
+    c->pool.push_back(pe.b);
+  }
+  c->pending.clear();
+}
+
+// One step on stream s: prologue and three fused stages; U^n is `state`, updated in place.
+// With timing on (direct launches only) every stage kernel is bracketed by an event pair.
+void enqueue_step(swe_hweno_ctx* c, double* state, int use_tend, hipStream_t s) {
+  const KArgs base = base_args(c);
+  const bool fa = (c->p.flags & SWE_FIXED_ALPHA) != 0;
+  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(64), 0, s, c->sc, c->p.dim, (c->p.flags & SWE_FIXED_DT) ? 1 : 0,
+                     c->p.fixed_dt, c->p.cfl, base.dx, base.dy, use_tend);
+  KArgs a = base;
+  a.S = state; a.out = c->S1; a.Dn_out = c->Dn;
+  a.a_in = fa ? c->sc->a_fix : c->sc->a_n; a.a_out = c->sc->a_1;
+  int id = time_begin(c, s);
+  launch_stage_mode<MODE_STAGE0>(c, a, s);
+  time_end(c, id, 1, s);
+  a = base;
+  a.S = c->S1; a.Sn = state; a.Dn = c->Dn; a.out = c->S2;
+  a.a_in = fa ? c->sc->a_fix : c->sc->a_1; a.a_out = c->sc->a_2;
+  id = time_begin(c, s);
+  launch_stage_mode<MODE_STAGE1>(c, a, s);
+  time_end(c, id, 2, s);
+  a = base;
+  a.S = c->S2; a.Sn = state; a.Dn = c->Dn; a.out = state;
+  a.a_in = fa ? c->sc->a_fix : c->sc->a_2; a.a_out = c->sc->a_next;
+  id = time_begin(c, s);
+  launch_stage_mode<MODE_STAGE2>(c, a, s);
+  time_end(c, id, 3, s);
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SWE_OK : SWE_EHIP; }
+
+int take_device_error(swe_hweno_ctx* c) {
+  int e = 0;
+  if (hipMemcpyAsync(&e, &c->sc->err, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
+  if (e) {
+    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, c->stream, c->sc);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
+    return (e & ERR_NONFINITE) ? SWE_ENONFINITE : SWE_EDRY;
+  }
+  return SWE_OK;
+}
+
+void destroy_graphs(swe_hweno_ctx* c) {
+  if (c->g1) hipGraphExecDestroy(c->g1);
+  if (c->g8) hipGraphExecDestroy(c->g8);
+  c->g1 = c->g8 = nullptr;
+  c->g_state = nullptr;
+}
+
+int capture(swe_hweno_ctx* c, double* state, int steps, int use_tend, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return SWE_EHIP;
+  for (int k = 0; k < steps; ++k) enqueue_step(c, state, use_tend, c->cap);
+  if (hipStreamEndCapture(c->cap, &g) != hipSuccess || !g) return SWE_EHIP;
+  const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_hweno_abi_version(void) { return SWE_HWENO_ABI_VERSION; }
+
+int swe_hweno_tile(int* cols_per_wave, int* rows_per_wave) {
+  if (!cols_per_wave || !rows_per_wave) return SWE_EINVAL;
+  *cols_per_wave = OUT_COLS;
+  *rows_per_wave = ROWS;
+  return SWE_OK;
+}
+
+const char* swe_hweno_strerror(int code) {
+  switch (code) {
+    case SWE_OK: return "ok";
+    case SWE_EINVAL: return "invalid argument";
+    case SWE_ENOMEM: return "device allocation failed";
+    case SWE_EHIP: return "HIP runtime error";
+    case SWE_EDRY: return "dry node (h <= 0)";
+    case SWE_ENONFINITE: return "non-finite value";
+    default: return "unknown error";
+  }
+}
+
+int swe_hweno_init(const swe_hweno_params* p, const double* b, const double* bx, const double* by, void* stream,
+                   swe_hweno_ctx** out) {
+  if (!out) return SWE_EINVAL;
+  *out = nullptr;
+  if (!params_ok(p) || !b || !bx || (p->dim == 2 && !by)) return SWE_EINVAL;
+  swe_hweno_ctx* c = new (std::nothrow) swe_hweno_ctx();
+  if (!c) return SWE_ENOMEM;
+  c->p = *p;
+  c->stream = (hipStream_t)stream;
+  c->nf = p->dim == 2 ? 9 : 4;
+  c->nd = p->dim == 2 ? 6 : 2;
+  c->n = (size_t)p->nx * (size_t)(p->dim == 2 ? p->ny : 1);
+  const size_t plane = c->n * sizeof(double);
+  bool ok = hipMalloc(&c->b, plane * 3) == hipSuccess;
+  ok = ok && hipMalloc(&c->S1, plane * c->nf) == hipSuccess;
+  ok = ok && hipMalloc(&c->S2, plane * c->nf) == hipSuccess;
+  ok = ok && hipMalloc(&c->Dn, plane * c->nd) == hipSuccess;
+  ok = ok && hipMalloc(&c->sc, sizeof(DevScal)) == hipSuccess;
+  if (!ok) { swe_hweno_destroy(c); return SWE_ENOMEM; }
+  c->bx = c->b + c->n;
+  c->by = c->b + 2 * c->n;
+  ok = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipMemcpyAsync(c->b, b, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(c->bx, bx, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  if (p->dim == 2) ok = ok && hipMemcpyAsync(c->by, by, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  else ok = ok && hipMemsetAsync(c->by, 0, plane, c->stream) == hipSuccess;
+  DevScal init;
+  std::memset(&init, 0, sizeof init);
+  init.a_fix[0] = dbits(p->alpha_x);
+  init.a_fix[1] = dbits(p->dim == 2 ? p->alpha_y : 0.0);
+  ok = ok && hipMemcpyAsync(c->sc, &init, sizeof init, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) { swe_hweno_destroy(c); return SWE_EHIP; }
+  *out = c;
+  return SWE_OK;
+}
+
+void swe_hweno_destroy(swe_hweno_ctx* c) {
+  if (!c) return;
+  if (c->stream || c->b) hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  collect_timing(c);
+  for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  if (c->cap) hipStreamDestroy(c->cap);
+  if (c->b) hipFree(c->b);
+  if (c->S1) hipFree(c->S1);
+  if (c->S2) hipFree(c->S2);
+  if (c->Dn) hipFree(c->Dn);
+  if (c->sc) hipFree(c->sc);
+  delete c;
+}
+
+int swe_hweno_rhs(swe_hweno_ctx* c, const double* state, double* rhs, double alpha_x, double alpha_y) {
+  if (!c || !state || !rhs || state == rhs) return SWE_EINVAL;
+  if (alpha_x >= 0 && (!(alpha_x > 0) || !std::isfinite(alpha_x))) return SWE_EINVAL;
+  if (alpha_x > 0 && c->p.dim == 2 && (!(alpha_y > 0) || !std::isfinite(alpha_y))) return SWE_EINVAL;
+  const size_t bytes = c->n * c->nf * sizeof(double);
+  if ((const char*)rhs < (const char*)state + bytes && (const char*)state < (const char*)rhs + bytes) return SWE_EINVAL;
+  if (alpha_x < 0) launch_alpha(c, state, c->sc->a_rhs, c->stream);
+  else
+    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, c->sc->a_rhs, dbits(alpha_x),
+                       dbits(c->p.dim == 2 ? alpha_y : 0.0));
+  KArgs a = base_args(c);
+  a.S = state; a.out = rhs; a.a_in = c->sc->a_rhs;
+  const int id = time_begin(c, c->stream);
+  launch_stage_mode<MODE_RHS>(c, a, c->stream);
+  time_end(c, id, 0, c->stream);
+  return hip_status(hipGetLastError());
+}
+
+int swe_hweno_limit(swe_hweno_ctx* c, const double* state, double* dmod) {
+  if (!c || !state || !dmod) return SWE_EINVAL;
+  KArgs a = base_args(c);
+  a.S = state; a.out = dmod;
+  const size_t blocks = (c->n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 8192 ? blocks : 8192);
+  if (c->p.dim == 2) hipLaunchKernelGGL(k_limit<2>, dim3(grid), dim3(256), 0, c->stream, a);
+  else hipLaunchKernelGGL(k_limit<1>, dim3(grid), dim3(256), 0, c->stream, a);
+  return hip_status(hipGetLastError());
+}
+
+int swe_hweno_alpha(swe_hweno_ctx* c, const double* state, double* alpha_host) {
+  if (!c || !state || !alpha_host) return SWE_EINVAL;
+  launch_alpha(c, state, c->sc->a_rhs, c->stream);
+  unsigned long long u[2];
+  if (hipMemcpyAsync(u, c->sc->a_rhs, sizeof u, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
+  const int e = take_device_error(c);
+  std::memcpy(&alpha_host[0], &u[0], 8);
+  std::memcpy(&alpha_host[1], &u[1], 8);
+  return e;
+}
+
+int swe_hweno_step(swe_hweno_ctx* c, double* state, double dt, double* dt_used) {
+  if (!c || !state) return SWE_EINVAL;
+  if (!(dt <= DBL_MAX)) return SWE_EINVAL;
+  const swe_hweno_params saved = c->p;
+  if (dt > 0) { c->p.flags |= SWE_FIXED_DT; c->p.fixed_dt = dt; }
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c->stream, c->sc, 0.0);
+  launch_alpha(c, state, c->sc->a_next, c->stream);
+  enqueue_step(c, state, 0, c->stream);
+  c->p = saved;
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  if (dt_used) {
+    if (hipMemcpyAsync(dt_used, &c->sc->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return SWE_EHIP;
+    return take_device_error(c);
+  }
+  return SWE_OK;
+}
+
+int swe_hweno_run(swe_hweno_ctx* c, double* state, int nsteps, double t_end, double* t_out, int* steps_out) {
+  if (!c || !state) return SWE_EINVAL;
+  if (!(t_end <= DBL_MAX) || (nsteps <= 0 && !(t_end > 0))) return SWE_EINVAL;
+  const int use_tend = t_end > 0 ? 1 : 0;
+  if (!c->timing && (c->g_state != state || c->g_tend != use_tend)) {
+    destroy_graphs(c);
+    int e = capture(c, state, 1, use_tend, &c->g1);
+    if (!e) e = capture(c, state, 8, use_tend, &c->g8);
+    if (e) { destroy_graphs(c); return e; }
+    c->g_state = state;
+    c->g_tend = use_tend;
+  }
+  // t = 0, t_end, steps = 0 and alpha of the initial state
+  {
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c->stream, c->sc, t_end);
+    launch_alpha(c, state, c->sc->a_next, c->stream);
+  }
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  int done = 0;
+  const int chunk = 64;
+  for (;;) {
+    int todo = nsteps > 0 ? nsteps - done : chunk;
+    if (todo <= 0) break;
+    if (use_tend && todo > chunk) todo = chunk;
+    int k = 0;
+    if (c->timing) {
+      for (; k < todo; ++k) enqueue_step(c, state, use_tend, c->stream);
+      if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+    }
+    for (; k + 8 <= todo; k += 8)
+      if (hipGraphLaunch(c->g8, c->stream) != hipSuccess) return SWE_EHIP;
+    for (; k < todo; ++k)
+      if (hipGraphLaunch(c->g1, c->stream) != hipSuccess) return SWE_EHIP;
+    done += todo;
+    if (use_tend) {
+      int active = 0;
+      if (hipMemcpyAsync(&active, &c->sc->active, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return SWE_EHIP;
+      if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
+      if (!active) break;
+    }
+  }
+  double t = 0;
+  int steps = 0;
+  if (hipMemcpyAsync(&t, &c->sc->t, sizeof t, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
+  if (hipMemcpyAsync(&steps, &c->sc->steps, sizeof steps, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return SWE_EHIP;
+  const int e = take_device_error(c);
+  if (c->timing) collect_timing(c);
+  if (t_out) *t_out = t;
+  if (steps_out) *steps_out = steps;
+  return e;
+}
+
+int swe_hweno_set_timing(swe_hweno_ctx* c, int on) {
+  if (!c) return SWE_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
+  collect_timing(c);
+  c->timing = on != 0;
+  for (int k = 0; k < 4; ++k) { c->ms[k] = 0; c->launches[k] = 0; }
+  return SWE_OK;
+}
+
+int swe_hweno_get_timing(swe_hweno_ctx* c, double* ms, long long* launches) {
+  if (!c || !ms || !launches) return SWE_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
+  collect_timing(c);
+  for (int k = 0; k < 4; ++k) { ms[k] = c->ms[k]; launches[k] = c->launches[k]; }
+  return SWE_OK;
+}
+
+int swe_hweno_sync(swe_hweno_ctx* c) {
+  if (!c) return SWE_EINVAL;
+  return take_device_error(c);
+}
+
+}  // extern "C"

@@ -311,3 +311,17 @@ def test_flop_count_is_stable(oracle_mod, inputs_mod):
         per.append((c["add"] + c["mul"] + c["div"] + c["sqrt"]) / n ** 2)
     assert 1500 < per[1] < 4000
     assert abs(per[0] - per[1]) / per[1] < 0.05
+
+
+def test_stored_flop_counts_are_current(oracle_mod):
+    """tests/golden/flop_counts.json (read by the benchmark's roofline) matches the oracle."""
+    import importlib.util
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(here, "make_flop_counts.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    stored = json.load(open(os.path.join(here, "flop_counts.json")))
+    fresh = mk.counts()
+    # (a one-time handful of constant initialisations may land in either count)
+    assert abs(stored["rhs_flops_per_node"] - fresh["rhs_flops_per_node"]) < 0.01
+    assert abs(stored["limiter_flops_per_node"] - fresh["limiter_flops_per_node"]) < 0.01
