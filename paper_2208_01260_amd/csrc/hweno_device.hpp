@@ -17,6 +17,17 @@ enum { S_ETA = 0, S_M, S_W, S_H1, S_M1, S_W1, S_H2, S_M2, S_W2, S_B, S_BX, S_BY,
 constexpr double K16 = 1.0 / 6.0, K112 = 1.0 / 12.0, K133 = 13.0 / 3.0, K1312 = 13.0 / 12.0;
 constexpr double K78120 = 781.0 / 20.0, K78180 = 781.0 / 80.0;
 
+// Reciprocal for operands in the normal range: hardware estimate refined by two Newton steps
+// (error below one unit in the last place; the inputs here are depths, wave speeds and sums of
+// squared smoothness indicators, never zero, denormal or infinite).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // One node seen from a sweep: U, its derivative along the sweep D, the normal flux F, its
 // derivative along the sweep P (Phi_1 for x, Psi_2 for y) and across it Q (the mixed term:
 // Psi_1 for x, Phi_2 for y), the bottom and its two derivatives.
@@ -43,7 +54,7 @@ __device__ __forceinline__ void node_frame(const double* __restrict__ r, double 
   const double dt2 = DIR == 0 ? r[S_W2] : r[S_M1];
   const double bn = DIR == 0 ? r[S_BX] : r[S_BY];
   const double bt = DIR == 0 ? r[S_BY] : r[S_BX];
-  const double h = e - b, ih = 1.0 / h;
+  const double h = e - b, ih = rcp(h);
   const double un = mn * ih, ut = mt * ih;
   const double j10 = g * h - un * un, j11 = 2.0 * un, j20 = -(un * ut);
   const double jb1 = un * un - g * e, jb2 = un * ut;
@@ -81,7 +92,7 @@ __device__ __forceinline__ double hweno_side(double f0, double f1, double f2, do
   const double e2 = (be2 + eps) * (be2 + eps);
   const double e3 = (be3 + eps) * (be3 + eps);
   const double u1 = 0.3 * (e2 * e3), u2 = 0.3 * (e1 * e3), u3 = 0.4 * (e1 * e2);
-  const double is = 1.0 / ((u1 + u2) + u3);
+  const double is = rcp((u1 + u2) + u3);
   w.w1 = u1 * is; w.w2 = u2 * is; w.w3 = u3 * is;
   const double q1 = 0.5 * (f0 + f1) + K16 * (s0 + 5.0 * s1);
   const double q2 = 0.5 * (f1 + f2) + K16 * (s1 - s2);
@@ -108,42 +119,79 @@ struct IfO {
   double MB;          // four-point central flux of the mixed bottom derivative (n component)
 };
 
-// A = node i-1, Bq = i, C = i+1, D = i+2; alpha = Lax-Friedrichs speed of this direction.
-__device__ __forceinline__ void interface_flux(const NodeF& A, const NodeF& Bq, const NodeF& C, const NodeF& D,
-                                               double alpha, double dx, double eps, double g, IfO& o) {
+// Interface x_{i+1/2} of a sweep. fetch(k, r) fills the raw record of node i-1+k (k = 0..3);
+// nodes are fetched, turned into fluxes and projected one at a time so that only one node's
+// derived quantities are live. alpha = Lax-Friedrichs speed of this direction.
+template <int DIR, class Fetch>
+__device__ __forceinline__ void interface_flux(Fetch fetch, double alpha, double dx, double eps, double g, IfO& o) {
+  double rB[NREC], rC[NREC];
+  fetch(1, rB);
+  fetch(2, rC);
   // characteristic matrices at the arithmetic mean of the two adjacent nodes
-  const double em = 0.5 * (Bq.e + C.e), mnm = 0.5 * (Bq.mn + C.mn), mtm = 0.5 * (Bq.mt + C.mt);
-  const double bm = 0.5 * (Bq.b + C.b);
-  const double h = em - bm, ih = 1.0 / h;
+  const double mnB = DIR == 0 ? rB[S_M] : rB[S_W], mtB = DIR == 0 ? rB[S_W] : rB[S_M];
+  const double mnC = DIR == 0 ? rC[S_M] : rC[S_W], mtC = DIR == 0 ? rC[S_W] : rC[S_M];
+  const double em = 0.5 * (rB[S_ETA] + rC[S_ETA]), mnm = 0.5 * (mnB + mnC), mtm = 0.5 * (mtB + mtC);
+  const double bm = 0.5 * (rB[S_B] + rC[S_B]);
+  const double h = em - bm, ih = rcp(h);
   const double un = mnm * ih, ut = mtm * ih;
-  const double cs = sqrt(g * h), i2c = 0.5 / cs;
+  const double cs = sqrt(g * h), i2c = 0.5 * rcp(cs);
   const double l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
   // rows: l1 = (l1a, -i2c, 0), l2 = (-ut, 0, 1), l3 = (l3a, i2c, 0)
   const double ha = 0.5 * alpha, hdx = 0.5 * dx, hadx = ha * dx;
 
   // projected, split values: f^± = (L F ± alpha L U)/2, s^± = dx (L P ± alpha L D)/2
   double fpA[3], spA[3], fpB[3], spB[3], fmB[3], smB[3], fpC[3], spC[3], fmC[3], smC[3], fmD[3], smD[3];
-#define SWE_PROJ(X, FP, SP, FM, SM, PLUS, MINUS)                                   \
-  {                                                                                \
+  double bA, bB, bC, bD, sbA, sbB, sbC, sbD;  // bottom and dx * its derivative along the sweep
+  double q1s[4], q7s[4];                      // partial sums of the mixed four-point flux
+#define SWE_PROJ(X, FP, SP, FM, SM, PLUS, MINUS)                                                  \
+  {                                                                                               \
     const double lf[3] = {l1a * X.f0 - i2c * X.f1, X.f2 - ut * X.f0, l3a * X.f0 + i2c * X.f1}; \
     const double lu[3] = {l1a * X.e - i2c * X.mn, X.mt - ut * X.e, l3a * X.e + i2c * X.mn};    \
     const double lp[3] = {l1a * X.p0 - i2c * X.p1, X.p2 - ut * X.p0, l3a * X.p0 + i2c * X.p1}; \
     const double ld[3] = {l1a * X.d0 - i2c * X.d1, X.d2 - ut * X.d0, l3a * X.d0 + i2c * X.d1}; \
-    _Pragma("unroll") for (int k = 0; k < 3; ++k) {                                \
-      if (PLUS) { FP[k] = 0.5 * lf[k] + ha * lu[k]; SP[k] = hdx * lp[k] + hadx * ld[k]; }    \
-      if (MINUS) { FM[k] = 0.5 * lf[k] - ha * lu[k]; SM[k] = hdx * lp[k] - hadx * ld[k]; }   \
-    }                                                                              \
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) {                                               \
+      if (PLUS) { FP[k] = 0.5 * lf[k] + ha * lu[k]; SP[k] = hdx * lp[k] + hadx * ld[k]; }         \
+      if (MINUS) { FM[k] = 0.5 * lf[k] - ha * lu[k]; SM[k] = hdx * lp[k] - hadx * ld[k]; }        \
+    }                                                                                             \
   }
   double dummy[3];
-  SWE_PROJ(A, fpA, spA, dummy, dummy, true, false)
-  SWE_PROJ(Bq, fpB, spB, fmB, smB, true, true)
-  SWE_PROJ(C, fpC, spC, fmC, smC, true, true)
-  SWE_PROJ(D, dummy, dummy, fmD, smD, false, true)
+  {
+    NodeF X;
+    node_frame<DIR>(rB, g, X);
+    SWE_PROJ(X, fpB, spB, fmB, smB, true, true)
+    bB = X.b; sbB = dx * X.bn;
+    q7s[0] = X.q0; q7s[1] = X.q1; q7s[2] = X.q2; q7s[3] = X.bt;
+  }
+  {
+    NodeF X;
+    node_frame<DIR>(rC, g, X);
+    SWE_PROJ(X, fpC, spC, fmC, smC, true, true)
+    bC = X.b; sbC = dx * X.bn;
+    q7s[0] += X.q0; q7s[1] += X.q1; q7s[2] += X.q2; q7s[3] += X.bt;
+  }
+  {
+    double rA[NREC];
+    fetch(0, rA);
+    NodeF X;
+    node_frame<DIR>(rA, g, X);
+    SWE_PROJ(X, fpA, spA, dummy, dummy, true, false)
+    bA = X.b; sbA = dx * X.bn;
+    q1s[0] = X.q0; q1s[1] = X.q1; q1s[2] = X.q2; q1s[3] = X.bt;
+  }
+  {
+    double rD[NREC];
+    fetch(3, rD);
+    NodeF X;
+    node_frame<DIR>(rD, g, X);
+    SWE_PROJ(X, dummy, dummy, fmD, smD, false, true)
+    bD = X.b; sbD = dx * X.bn;
+    q1s[0] += X.q0; q1s[1] += X.q1; q1s[2] += X.q2; q1s[3] += X.bt;
+  }
 #undef SWE_PROJ
 
-  // candidate values of the (unprojected) bottom b with derivatives dx*B_n, both orientations
-  const double sbA = dx * A.bn, sbB = dx * Bq.bn, sbC = dx * C.bn, sbD = dx * D.bn;
-  double s[3], Z1 = 0.0, Z3 = 0.0;
+  // nonlinear reconstruction per characteristic field and side; the bottom reuses the weights
+  const double i4dx = 0.25 / dx, i12dx = K112 / dx;
+  double s[3], t[3], Z1 = 0.0, Z3 = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     W3 wp, wm;
@@ -151,9 +199,12 @@ __device__ __forceinline__ void interface_flux(const NodeF& A, const NodeF& Bq, 
     const double vm = hweno_side(fmD[k], fmC[k], fmB[k], -smD[k], -smC[k], -smB[k], eps, wm);
     s[k] = vp + vm;
     if (k != 1) {  // the middle characteristic row annihilates (0, b, 0)
-      const double z = hweno_with(A.b, Bq.b, C.b, sbA, sbB, sbC, wp) + hweno_with(D.b, C.b, Bq.b, -sbD, -sbC, -sbB, wm);
+      const double z = hweno_with(bA, bB, bC, sbA, sbB, sbC, wp) + hweno_with(bD, bC, bB, -sbD, -sbC, -sbB, wm);
       if (k == 0) Z1 = z; else Z3 = z;
     }
+    // linear Hermite derivative Q'^+(f^+, s^+/dx) + Q'^-(f^-, s^-/dx) of this characteristic field
+    t[k] = ((fpA[k] - fmD[k]) + 8.0 * (fmC[k] - fpB[k]) + 7.0 * (fpC[k] - fmB[k])) * i4dx +
+           ((spA[k] + smD[k]) - 2.0 * (spB[k] + smC[k]) - 5.0 * (spC[k] + smB[k])) * i12dx;
   }
   // back to the conservative frame: R columns (1, un-c, ut), (0, 0, 1), (1, un+c, ut)
   const double umc = un - cs, upc = un + cs;
@@ -165,27 +216,17 @@ __device__ __forceinline__ void interface_flux(const NodeF& A, const NodeF& Bq, 
   o.B0 = sb1 + sb3;
   o.B1 = umc * sb1 + upc * sb3;
   o.B2 = ut * (sb1 + sb3);
-
-  // linear Hermite fluxes Q'^+(F^+, P^+) + Q'^-(F^-, P^-), componentwise, expanded in F, P, U, D
-  const double i4dx = 0.25 / dx;
-#define SWE_DQ(fa, fb, fc, fd, pa, pb, pc, pd) \
-  (((fa - fd) + 15.0 * (fc - fb)) * i4dx + K112 * ((pa + pd) - 7.0 * (pb + pc)))
-#define SWE_DQD(fa, fb, fc, fd, pa, pb, pc, pd) \
-  (((fa + fd) - (fb + fc)) * i4dx + K112 * ((pa - pd) + 3.0 * (pb - pc)))
-  o.P0 = 0.5 * SWE_DQ(A.f0, Bq.f0, C.f0, D.f0, A.p0, Bq.p0, C.p0, D.p0) +
-         ha * SWE_DQD(A.e, Bq.e, C.e, D.e, A.d0, Bq.d0, C.d0, D.d0);
-  o.P1 = 0.5 * SWE_DQ(A.f1, Bq.f1, C.f1, D.f1, A.p1, Bq.p1, C.p1, D.p1) +
-         ha * SWE_DQD(A.mn, Bq.mn, C.mn, D.mn, A.d1, Bq.d1, C.d1, D.d1);
-  o.P2 = 0.5 * SWE_DQ(A.f2, Bq.f2, C.f2, D.f2, A.p2, Bq.p2, C.p2, D.p2) +
-         ha * SWE_DQD(A.mt, Bq.mt, C.mt, D.mt, A.d2, Bq.d2, C.d2, D.d2);
-  o.PB = 0.5 * SWE_DQ(A.b, Bq.b, C.b, D.b, A.bn, Bq.bn, C.bn, D.bn);
-#undef SWE_DQ
-#undef SWE_DQD
+  // the linear derivative-equation flux: componentwise Q' is R (char.-wise Q') since L is fixed
+  o.P0 = t[0] + t[2];
+  o.P1 = umc * t[0] + upc * t[2];
+  o.P2 = ut * (t[0] + t[2]) + t[1];
+  // bottom derivative, n component: Q'^+(b/2, B/2) + Q'^-(b/2, B/2)
+  o.PB = 0.5 * (((bA - bD) + 15.0 * (bC - bB)) * i4dx + ((sbA + sbD) - 7.0 * (sbB + sbC)) * i12dx);
   // four-point central flux of the mixed terms (eq. (3.7))
-  o.M0 = K112 * (7.0 * (Bq.q0 + C.q0) - (A.q0 + D.q0));
-  o.M1 = K112 * (7.0 * (Bq.q1 + C.q1) - (A.q1 + D.q1));
-  o.M2 = K112 * (7.0 * (Bq.q2 + C.q2) - (A.q2 + D.q2));
-  o.MB = K112 * (7.0 * (Bq.bt + C.bt) - (A.bt + D.bt));
+  o.M0 = K112 * (7.0 * q7s[0] - q1s[0]);
+  o.M1 = K112 * (7.0 * q7s[1] - q1s[1]);
+  o.M2 = K112 * (7.0 * q7s[2] - q1s[2]);
+  o.MB = K112 * (7.0 * q7s[3] - q1s[3]);
 }
 
 // HWENO limiter of one characteristic component (Sec. 2.2): mu at x_{i-1}, x_i, x_{i+1}, nu at
@@ -201,7 +242,7 @@ __device__ __forceinline__ double limit_char(double mm, double m0, double mp, do
   const double be3 = a3 * a3 + K1312 * (c3 * c3);
   const double e1 = (be1 + eps) * (be1 + eps), e2 = (be2 + eps) * (be2 + eps), e3 = (be3 + eps) * (be3 + eps);
   const double u1 = 0.25 * (e2 * e3), u2 = 0.25 * (e1 * e3), u3 = 0.5 * (e1 * e2);
-  const double is = 1.0 / ((u1 + u2) + u3);
+  const double is = rcp((u1 + u2) + u3);
   return ((u1 * a1 + u2 * a2) + u3 * a3) * is * idx;
 }
 
@@ -211,9 +252,9 @@ __device__ __forceinline__ void limit_frame(double e0, double mn0, double mt0, d
                                             double mtm, double ep, double mnp, double mtp, double dm0, double dm1,
                                             double dm2, double dp0, double dp1, double dp2, double dx, double idx,
                                             double eps, double g, double out[3]) {
-  const double h = e0 - b0, ih = 1.0 / h;
+  const double h = e0 - b0, ih = rcp(h);
   const double un = mn0 * ih, ut = mt0 * ih;
-  const double cs = sqrt(g * h), i2c = 0.5 / cs;
+  const double cs = sqrt(g * h), i2c = 0.5 * rcp(cs);
   const double l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
   const double v1 = limit_char(l1a * em - i2c * mnm, l1a * e0 - i2c * mn0, l1a * ep - i2c * mnp,
                                l1a * dm0 - i2c * dm1, l1a * dp0 - i2c * dp1, dx, idx, eps);

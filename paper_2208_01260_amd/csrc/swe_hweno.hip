@@ -100,17 +100,6 @@ __device__ __forceinline__ void load_rec(const KArgs& a, const double* __restric
   if (ry) { r[S_W] = -r[S_W]; r[S_W1] = -r[S_W1]; r[S_H2] = -r[S_H2]; r[S_M2] = -r[S_M2]; r[S_BY] = -r[S_BY]; }
 }
 
-template <int DIR>
-__device__ __forceinline__ void iface(const double* r0, const double* r1, const double* r2, const double* r3,
-                                      double alpha, double h, const KArgs& a, IfO& o) {
-  NodeF A, B, C, D;
-  node_frame<DIR>(r0, a.g, A);
-  node_frame<DIR>(r1, a.g, B);
-  node_frame<DIR>(r2, a.g, C);
-  node_frame<DIR>(r3, a.g, D);
-  interface_flux(A, B, C, D, alpha, h, a.eps, a.g, o);
-}
-
 __device__ __forceinline__ void ifo_to_array(const IfO& o, double* v) {
   v[0] = o.F0; v[1] = o.F1; v[2] = o.F2; v[3] = o.B0; v[4] = o.B1; v[5] = o.B2; v[6] = o.P0;
   v[7] = o.P1; v[8] = o.P2; v[9] = o.PB; v[10] = o.M0; v[11] = o.M1; v[12] = o.M2; v[13] = o.MB;
@@ -181,14 +170,17 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
   const int r0 = DIM == 2 ? blockIdx.y * ROWS : 0;
   const int r1 = DIM == 2 ? min(r0 + ROWS, a.ny) : 1;
   const bool col_out = lane >= 2 && lane < WAVE - 2 && c < a.nx;
+  const int cq = col_out ? c : 0;  // a column that is always inside the grid
   const double axl = bits2d(a.a_in[0]), ayl = bits2d(a.a_in[1]);
   const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
   const double dt = MODE == MODE_RHS ? 0.0 : a.sc->dt;
+  const int nu = DIM == 2 ? 3 : 2, nd = DIM == 2 ? 6 : 2;
+  const int la = max(lane - 2, 0), lb = max(lane - 1, 0), ld = min(lane + 1, WAVE - 1);
   double amx = 0.0, amy = 0.0;
   int err = 0;
 
-  // y window: rows r-1, r, r+1, r+2 (2D only) and the flux of interface r-1/2
-  double wm1[NREC], w0[NREC], wp1[NREC], wp2[NREC], nxt[NREC];
+  // y window: raw records of rows r-1, r, r+1 and the flux of interface r-1/2 (2D only)
+  double wm1[NREC], w0[NREC], wp1[NREC];
   double yprev[14];
   if (DIM == 2) {
     double wm2[NREC];
@@ -196,53 +188,81 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
     load_rec<DIM>(a, a.S, c, r0 - 1, wm1);
     load_rec<DIM>(a, a.S, c, r0, w0);
     load_rec<DIM>(a, a.S, c, r0 + 1, wp1);
-    load_rec<DIM>(a, a.S, c, r0 + 2, nxt);
     IfO o;
-    iface<1>(wm2, wm1, w0, wp1, ayl, a.dy, a, o);
+    auto fy = [&](int k, double* r) {
+      const double* src = k == 0 ? wm2 : (k == 1 ? wm1 : (k == 2 ? w0 : wp1));
+#pragma unroll
+      for (int f = 0; f < NREC; ++f) r[f] = src[f];
+    };
+    interface_flux<1>(fy, ayl, a.dy, a.eps, a.g, o);
     ifo_to_array(o, yprev);
   } else {
     load_rec<DIM>(a, a.S, c, 0, w0);
   }
 
   for (int r = r0; r < r1; ++r) {
+    const size_t q = (size_t)r * a.nx + cq;
+    // loads whose latency the x-sweep hides: the next row of the window, U^n and D^{n,mod}
+    double wp2[NREC];
+    if (DIM == 2) load_rec<DIM>(a, a.S, c, r + 2, wp2);
+    double un_[3], dn_[6];
+    if (MODE == MODE_STAGE1 || MODE == MODE_STAGE2) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) if (k < nu) un_[k] = a.Sn[k * n + q];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) if (k < nd) dn_[k] = a.Dn[k * n + q];
+    }
     double R[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = 0.0;
-    double ynew[14];
-    if (DIM == 2) {
-#pragma unroll
-      for (int k = 0; k < NREC; ++k) wp2[k] = nxt[k];
-      if (r + 1 < r1) load_rec<DIM>(a, a.S, c, r + 3, nxt);  // prefetch for the next row
-      IfO o;
-      iface<1>(wm1, w0, wp1, wp2, ayl, a.dy, a, o);
-      ifo_to_array(o, ynew);
-    }
-    // x-sweep of row r: neighbours through LDS
+
+    // x-sweep of row r: raw records exchanged through LDS, read when needed
 #pragma unroll
     for (int k = 0; k < NREC; ++k) sx[k][lane] = w0[k];
     __syncthreads();
-    const int la = max(lane - 2, 0), lb = max(lane - 1, 0), ld = min(lane + 1, WAVE - 1);
-    double xa[NREC], xb[NREC], xd[NREC];
-#pragma unroll
-    for (int k = 0; k < NREC; ++k) { xa[k] = sx[k][la]; xb[k] = sx[k][lb]; xd[k] = sx[k][ld]; }
     double xl[14];
     {
       IfO o;
-      iface<0>(xa, xb, w0, xd, axl, a.dx, a, o);
+      auto fx = [&](int k, double* r) {
+        if (k == 2) {
+#pragma unroll
+          for (int f = 0; f < NREC; ++f) r[f] = w0[f];
+        } else {
+          const int l = k == 0 ? la : (k == 1 ? lb : ld);
+#pragma unroll
+          for (int f = 0; f < NREC; ++f) r[f] = sx[f][l];
+        }
+      };
+      interface_flux<0>(fx, axl, a.dx, a.eps, a.g, o);
       ifo_to_array(o, xl);
     }
 #pragma unroll
     for (int k = 0; k < 14; ++k) sf[k][lane] = xl[k];
     __syncthreads();
-    double xr[14];
+    const double eta = w0[S_ETA], H1 = w0[S_H1], H2 = w0[S_H2];
+    {
+      double xr[14];
 #pragma unroll
-    for (int k = 0; k < 14; ++k) xr[k] = sf[k][ld];
+      for (int k = 0; k < 14; ++k) xr[k] = sf[k][ld];
+      assemble<0>(xl, xr, eta, H1, H2, a.g, a.idx, R);
+    }
+    // y-sweep: interface r+1/2 from rows r-1 .. r+2
+    if (DIM == 2) {
+      double ynew[14];
+      IfO o;
+      auto fy = [&](int k, double* r) {
+        const double* src = k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2));
+#pragma unroll
+        for (int f = 0; f < NREC; ++f) r[f] = src[f];
+      };
+      interface_flux<1>(fy, ayl, a.dy, a.eps, a.g, o);
+      ifo_to_array(o, ynew);
+      assemble<1>(yprev, ynew, eta, H1, H2, a.g, a.idy, R);
+#pragma unroll
+      for (int k = 0; k < 14; ++k) yprev[k] = ynew[k];
+    }
 
     if (col_out) {
-      const double eta = w0[S_ETA], H1 = w0[S_H1], H2 = w0[S_H2];
-      assemble<0>(xl, xr, eta, H1, H2, a.g, a.idx, R);
-      if (DIM == 2) assemble<1>(yprev, ynew, eta, H1, H2, a.g, a.idy, R);
-      const size_t q = (size_t)r * a.nx + c;
       if (MODE == MODE_RHS) {
         if (DIM == 2) {
 #pragma unroll
@@ -254,9 +274,9 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
         // limited derivatives of this stage's state at the node (Sec. 2.2)
         double Dm[6];
         if (a.limiter) {
-          limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], xb[S_ETA], xb[S_M], xb[S_W], xd[S_ETA], xd[S_M],
-                      xd[S_W], xb[S_H1], xb[S_M1], xb[S_W1], xd[S_H1], xd[S_M1], xd[S_W1], a.dx, a.idx, a.eps, a.g,
-                      Dm);
+          limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], sx[S_ETA][lb], sx[S_M][lb], sx[S_W][lb],
+                      sx[S_ETA][ld], sx[S_M][ld], sx[S_W][ld], sx[S_H1][lb], sx[S_M1][lb], sx[S_W1][lb],
+                      sx[S_H1][ld], sx[S_M1][ld], sx[S_W1][ld], a.dx, a.idx, a.eps, a.g, Dm);
           if (DIM == 2) {
             double o3[3];
             limit_frame(w0[S_ETA], w0[S_W], w0[S_M], w0[S_B], wm1[S_ETA], wm1[S_W], wm1[S_M], wp1[S_ETA],
@@ -269,18 +289,17 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
           Dm[3] = w0[S_H2]; Dm[4] = w0[S_M2]; Dm[5] = w0[S_W2];
         }
         // SSP-RK3 combination (eq. (2.11)), written over a common denominator
-        const int nu = DIM == 2 ? 3 : 2, nd = DIM == 2 ? 6 : 2;
         const int uslot[3] = {S_ETA, S_M, S_W};
         const int rd[6] = {3, 4, 5, 6, 7, 8};
-        double Unew[3];
+        double Unew[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (k >= nu) break;
           const double u = w0[uslot[k]] + dt * R[k];
           double v;
           if (MODE == MODE_STAGE0) v = u;
-          else if (MODE == MODE_STAGE1) v = (3.0 * a.Sn[k * n + q] + u) * 0.25;
-          else v = (a.Sn[k * n + q] + 2.0 * u) / 3.0;
+          else if (MODE == MODE_STAGE1) v = (3.0 * un_[k] + u) * 0.25;
+          else v = (un_[k] + 2.0 * u) / 3.0;
           Unew[k] = v;
           a.out[k * n + q] = v;
         }
@@ -293,18 +312,16 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
             v = u;
             a.Dn_out[k * n + q] = Dm[k];
           } else if (MODE == MODE_STAGE1) {
-            v = (3.0 * a.Dn[k * n + q] + u) * 0.25;
+            v = (3.0 * dn_[k] + u) * 0.25;
           } else {
-            v = (a.Dn[k * n + q] + 2.0 * u) / 3.0;
+            v = (dn_[k] + 2.0 * u) / 3.0;
           }
           a.out[(nu + k) * n + q] = v;
         }
-        speeds(Unew[0], Unew[1], DIM == 2 ? Unew[2] : 0.0, w0[S_B], a.g, amx, amy, err);
+        speeds(Unew[0], Unew[1], Unew[2], w0[S_B], a.g, amx, amy, err);
       }
     }
     if (DIM == 2) {
-#pragma unroll
-      for (int k = 0; k < 14; ++k) yprev[k] = ynew[k];
 #pragma unroll
       for (int k = 0; k < NREC; ++k) { wm1[k] = w0[k]; w0[k] = wp1[k]; wp1[k] = wp2[k]; }
     }
