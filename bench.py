@@ -113,6 +113,7 @@ def main():
     state0 = torch.from_numpy(pr.state).to(dev).contiguous()
     st = state0.clone()
     s = Solver.from_problem(pr, device=dev)
+    tile = s.tile()
     torch.cuda.synchronize()
 
     # warm-up (graph path), then the graph path timed for reference
@@ -190,6 +191,7 @@ def main():
         "roofline": roof,
         "rhs_kernel": rhs_kernel,
         "graph_replay_ms_per_step": graph_ms,
+        "tile": {"cols_per_wave": tile[0], "rows_per_wave": tile[1]},
         "cell_steps_per_s": cells * args.steps / wall,
     }
     if not args.no_cpu:

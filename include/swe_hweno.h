@@ -127,9 +127,13 @@ int swe_hweno_abi_version(void);
 int swe_hweno_set_timing(swe_hweno_ctx* ctx, int on);
 int swe_hweno_get_timing(swe_hweno_ctx* ctx, double* ms, long long* launches);
 
-/* Dimensions of the fused stage kernel's tiles (columns of output per wavefront and rows per
- * wavefront march); for tests and benchmarks. Host-only, no HIP call. */
+/* Dimensions of the fused stage kernel's tiles (columns of output per wavefront and the default
+ * rows per wavefront march); for tests and benchmarks. Host-only, no HIP call. */
 int swe_hweno_tile(int* cols_per_wave, int* rows_per_wave);
+
+/* The tile a context uses: rows per march are chosen at init from the grid and the device's
+ * compute-unit count (environment variable SWE_HWENO_ROWS overrides). Host-only. */
+int swe_hweno_ctx_tile(const swe_hweno_ctx* ctx, int* cols_per_wave, int* rows_per_wave);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libswe_hweno.so")
+# SWE_HWENO_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SWE_HWENO_LIB") or os.path.join(HERE, "libswe_hweno.so")
 
 OK, EINVAL, ENOMEM, EHIP, EDRY, ENONFINITE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_REFLECTIVE = 0, 1
@@ -20,7 +21,7 @@ ABI_VERSION = 1
 # every symbol include/swe_hweno.h declares
 EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alpha", "swe_hweno_step",
            "swe_hweno_run", "swe_hweno_sync", "swe_hweno_destroy", "swe_hweno_strerror", "swe_hweno_abi_version",
-           "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing")
+           "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing", "swe_hweno_ctx_tile")
 
 
 class SweError(RuntimeError):
@@ -64,6 +65,7 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_abi_version": (I, []),
         "swe_hweno_tile": (I, [ctypes.POINTER(I), ctypes.POINTER(I)]),
         "swe_hweno_set_timing": (I, [vp, I]),
+        "swe_hweno_ctx_tile": (I, [vp, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "swe_hweno_get_timing": (I, [vp, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
     }
     for name, (res, args) in sig.items():

@@ -19,8 +19,8 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + [SRC, "-o", OUT + ".tmp"]
+def build(verbose: bool = False, out: str = OUT, defines=()) -> str:
+    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + [SRC, "-o", out + ".tmp"]
     if verbose:
         cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -29,8 +29,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed for " + SRC)
     if verbose:
         sys.stderr.write(r.stderr)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

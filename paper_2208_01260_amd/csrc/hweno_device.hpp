@@ -119,19 +119,18 @@ struct IfO {
   double MB;          // four-point central flux of the mixed bottom derivative (n component)
 };
 
-// Interface x_{i+1/2} of a sweep. fetch(k, r) fills the raw record of node i-1+k (k = 0..3);
-// nodes are fetched, turned into fluxes and projected one at a time so that only one node's
-// derived quantities are live. alpha = Lax-Friedrichs speed of this direction.
-template <int DIR, class Fetch>
+// Interface x_{i+1/2} of a sweep. fetch(k, X) provides the fluxes of node i-1+k (k = 0..3),
+// either computed from a raw record or read from where another lane left them; nodes are
+// fetched and projected one at a time so that only one node's quantities are live.
+// alpha = Lax-Friedrichs speed of this direction.
+template <class Fetch>
 __device__ __forceinline__ void interface_flux(Fetch fetch, double alpha, double dx, double eps, double g, IfO& o) {
-  double rB[NREC], rC[NREC];
-  fetch(1, rB);
-  fetch(2, rC);
+  NodeF XB, XC;
+  fetch(1, XB);
+  fetch(2, XC);
   // characteristic matrices at the arithmetic mean of the two adjacent nodes
-  const double mnB = DIR == 0 ? rB[S_M] : rB[S_W], mtB = DIR == 0 ? rB[S_W] : rB[S_M];
-  const double mnC = DIR == 0 ? rC[S_M] : rC[S_W], mtC = DIR == 0 ? rC[S_W] : rC[S_M];
-  const double em = 0.5 * (rB[S_ETA] + rC[S_ETA]), mnm = 0.5 * (mnB + mnC), mtm = 0.5 * (mtB + mtC);
-  const double bm = 0.5 * (rB[S_B] + rC[S_B]);
+  const double em = 0.5 * (XB.e + XC.e), mnm = 0.5 * (XB.mn + XC.mn), mtm = 0.5 * (XB.mt + XC.mt);
+  const double bm = 0.5 * (XB.b + XC.b);
   const double h = em - bm, ih = rcp(h);
   const double un = mnm * ih, ut = mtm * ih;
   const double cs = sqrt(g * h), i2c = 0.5 * rcp(cs);
@@ -155,34 +154,22 @@ __device__ __forceinline__ void interface_flux(Fetch fetch, double alpha, double
     }                                                                                             \
   }
   double dummy[3];
+  SWE_PROJ(XB, fpB, spB, fmB, smB, true, true)
+  bB = XB.b; sbB = dx * XB.bn;
+  q7s[0] = XB.q0; q7s[1] = XB.q1; q7s[2] = XB.q2; q7s[3] = XB.bt;
+  SWE_PROJ(XC, fpC, spC, fmC, smC, true, true)
+  bC = XC.b; sbC = dx * XC.bn;
+  q7s[0] += XC.q0; q7s[1] += XC.q1; q7s[2] += XC.q2; q7s[3] += XC.bt;
   {
     NodeF X;
-    node_frame<DIR>(rB, g, X);
-    SWE_PROJ(X, fpB, spB, fmB, smB, true, true)
-    bB = X.b; sbB = dx * X.bn;
-    q7s[0] = X.q0; q7s[1] = X.q1; q7s[2] = X.q2; q7s[3] = X.bt;
-  }
-  {
-    NodeF X;
-    node_frame<DIR>(rC, g, X);
-    SWE_PROJ(X, fpC, spC, fmC, smC, true, true)
-    bC = X.b; sbC = dx * X.bn;
-    q7s[0] += X.q0; q7s[1] += X.q1; q7s[2] += X.q2; q7s[3] += X.bt;
-  }
-  {
-    double rA[NREC];
-    fetch(0, rA);
-    NodeF X;
-    node_frame<DIR>(rA, g, X);
+    fetch(0, X);
     SWE_PROJ(X, fpA, spA, dummy, dummy, true, false)
     bA = X.b; sbA = dx * X.bn;
     q1s[0] = X.q0; q1s[1] = X.q1; q1s[2] = X.q2; q1s[3] = X.bt;
   }
   {
-    double rD[NREC];
-    fetch(3, rD);
     NodeF X;
-    node_frame<DIR>(rD, g, X);
+    fetch(3, X);
     SWE_PROJ(X, dummy, dummy, fmD, smD, false, true)
     bD = X.b; sbD = dx * X.bn;
     q1s[0] += X.q0; q1s[1] += X.q1; q1s[2] += X.q2; q1s[3] += X.bt;

@@ -19,8 +19,10 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "hweno_device.hpp"
@@ -30,7 +32,7 @@ namespace swe {
 
 constexpr int WAVE = 64;
 constexpr int OUT_COLS = WAVE - 4;  // interior columns written per wave
-constexpr int ROWS = 32;            // rows marched per wave
+constexpr int ROWS_DEFAULT = 32;    // rows marched per wave unless tuned
 
 enum { MODE_RHS = 0, MODE_STAGE0 = 1, MODE_STAGE1 = 2, MODE_STAGE2 = 3 };
 enum { ERR_DRY = 1, ERR_NONFINITE = 2 };
@@ -59,7 +61,7 @@ struct KArgs {
   const unsigned long long* a_in;  // Lax-Friedrichs speeds used
   unsigned long long* a_out;       // max-reduction of the output state's speeds
   DevScal* sc;
-  int nx, ny, bcx, bcy, limiter;
+  int nx, ny, bcx, bcy, limiter, rows;
   double dx, dy, idx, idy, g, eps;
 };
 
@@ -98,6 +100,20 @@ __device__ __forceinline__ void load_rec(const KArgs& a, const double* __restric
   }
   if (rx) { r[S_M] = -r[S_M]; r[S_H1] = -r[S_H1]; r[S_W1] = -r[S_W1]; r[S_M2] = -r[S_M2]; r[S_BX] = -r[S_BX]; }
   if (ry) { r[S_W] = -r[S_W]; r[S_W1] = -r[S_W1]; r[S_H2] = -r[S_H2]; r[S_M2] = -r[S_M2]; r[S_BY] = -r[S_BY]; }
+}
+
+// Node fluxes through LDS: slot k of a NodeF at lane l is sn[k][l].
+constexpr int NNODE = 18;
+__device__ __forceinline__ void nodef_store(double (*sn)[64], int l, const NodeF& X) {
+  const double v[NNODE] = {X.e, X.mn, X.mt, X.d0, X.d1, X.d2, X.f0, X.f1, X.f2,
+                           X.p0, X.p1, X.p2, X.q0, X.q1, X.q2, X.b, X.bn, X.bt};
+#pragma unroll
+  for (int k = 0; k < NNODE; ++k) sn[k][l] = v[k];
+}
+__device__ __forceinline__ void nodef_load(double (*sn)[64], int l, NodeF& X) {
+  X.e = sn[0][l]; X.mn = sn[1][l]; X.mt = sn[2][l]; X.d0 = sn[3][l]; X.d1 = sn[4][l]; X.d2 = sn[5][l];
+  X.f0 = sn[6][l]; X.f1 = sn[7][l]; X.f2 = sn[8][l]; X.p0 = sn[9][l]; X.p1 = sn[10][l]; X.p2 = sn[11][l];
+  X.q0 = sn[12][l]; X.q1 = sn[13][l]; X.q2 = sn[14][l]; X.b = sn[15][l]; X.bn = sn[16][l]; X.bt = sn[17][l];
 }
 
 __device__ __forceinline__ void ifo_to_array(const IfO& o, double* v) {
@@ -163,12 +179,13 @@ __device__ __forceinline__ void flush_speeds(const KArgs& a, double ax, double a
 template <int DIM, int MODE>
 __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
   if (MODE != MODE_RHS && a.sc->active == 0) return;
-  __shared__ double sx[NREC][WAVE];
-  __shared__ double sf[14][WAVE];
+  __shared__ double sn[NNODE][WAVE];  // x-frame fluxes of the current row, one node per lane
+  __shared__ double sf[14][WAVE];     // x-interface quantities (lane l: interface left of its column)
+  __shared__ double sy[14][WAVE];     // y-interface quantities of the previous row (own lane)
   const int lane = threadIdx.x;
   const int c = blockIdx.x * OUT_COLS - 2 + lane;  // this lane's column
-  const int r0 = DIM == 2 ? blockIdx.y * ROWS : 0;
-  const int r1 = DIM == 2 ? min(r0 + ROWS, a.ny) : 1;
+  const int r0 = DIM == 2 ? blockIdx.y * a.rows : 0;
+  const int r1 = DIM == 2 ? min(r0 + a.rows, a.ny) : 1;
   const bool col_out = lane >= 2 && lane < WAVE - 2 && c < a.nx;
   const int cq = col_out ? c : 0;  // a column that is always inside the grid
   const double axl = bits2d(a.a_in[0]), ayl = bits2d(a.a_in[1]);
@@ -179,9 +196,8 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
   double amx = 0.0, amy = 0.0;
   int err = 0;
 
-  // y window: raw records of rows r-1, r, r+1 and the flux of interface r-1/2 (2D only)
+  // y window: raw records of rows r-1, r, r+1 (2D); the flux of interface r-1/2 waits in sy
   double wm1[NREC], w0[NREC], wp1[NREC];
-  double yprev[14];
   if (DIM == 2) {
     double wm2[NREC];
     load_rec<DIM>(a, a.S, c, r0 - 2, wm2);
@@ -189,13 +205,14 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
     load_rec<DIM>(a, a.S, c, r0, w0);
     load_rec<DIM>(a, a.S, c, r0 + 1, wp1);
     IfO o;
-    auto fy = [&](int k, double* r) {
-      const double* src = k == 0 ? wm2 : (k == 1 ? wm1 : (k == 2 ? w0 : wp1));
-#pragma unroll
-      for (int f = 0; f < NREC; ++f) r[f] = src[f];
+    auto fy = [&](int k, NodeF& X) {
+      node_frame<1>(k == 0 ? wm2 : (k == 1 ? wm1 : (k == 2 ? w0 : wp1)), a.g, X);
     };
-    interface_flux<1>(fy, ayl, a.dy, a.eps, a.g, o);
-    ifo_to_array(o, yprev);
+    interface_flux(fy, ayl, a.dy, a.eps, a.g, o);
+    double v[14];
+    ifo_to_array(o, v);
+#pragma unroll
+    for (int k = 0; k < 14; ++k) sy[k][lane] = v[k];
   } else {
     load_rec<DIM>(a, a.S, c, 0, w0);
   }
@@ -215,32 +232,26 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
     double R[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = 0.0;
-
-    // x-sweep of row r: raw records exchanged through LDS, read when needed
-#pragma unroll
-    for (int k = 0; k < NREC; ++k) sx[k][lane] = w0[k];
-    __syncthreads();
-    double xl[14];
-    {
-      IfO o;
-      auto fx = [&](int k, double* r) {
-        if (k == 2) {
-#pragma unroll
-          for (int f = 0; f < NREC; ++f) r[f] = w0[f];
-        } else {
-          const int l = k == 0 ? la : (k == 1 ? lb : ld);
-#pragma unroll
-          for (int f = 0; f < NREC; ++f) r[f] = sx[f][l];
-        }
-      };
-      interface_flux<0>(fx, axl, a.dx, a.eps, a.g, o);
-      ifo_to_array(o, xl);
-    }
-#pragma unroll
-    for (int k = 0; k < 14; ++k) sf[k][lane] = xl[k];
-    __syncthreads();
     const double eta = w0[S_ETA], H1 = w0[S_H1], H2 = w0[S_H2];
+
+    // x-sweep of row r: each lane's x-frame fluxes are computed once and shared through LDS
+    __syncthreads();  // the previous row's readers of sn and sf are done
     {
+      NodeF me;
+      node_frame<0>(w0, a.g, me);
+      nodef_store(sn, lane, me);
+      __syncthreads();
+      IfO o;
+      auto fx = [&](int k, NodeF& X) {
+        if (k == 2) X = me;
+        else nodef_load(sn, k == 0 ? la : (k == 1 ? lb : ld), X);
+      };
+      interface_flux(fx, axl, a.dx, a.eps, a.g, o);
+      double xl[14];
+      ifo_to_array(o, xl);
+#pragma unroll
+      for (int k = 0; k < 14; ++k) sf[k][lane] = xl[k];
+      __syncthreads();
       double xr[14];
 #pragma unroll
       for (int k = 0; k < 14; ++k) xr[k] = sf[k][ld];
@@ -248,18 +259,16 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
     }
     // y-sweep: interface r+1/2 from rows r-1 .. r+2
     if (DIM == 2) {
-      double ynew[14];
       IfO o;
-      auto fy = [&](int k, double* r) {
-        const double* src = k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2));
-#pragma unroll
-        for (int f = 0; f < NREC; ++f) r[f] = src[f];
+      auto fy = [&](int k, NodeF& X) {
+        node_frame<1>(k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2)), a.g, X);
       };
-      interface_flux<1>(fy, ayl, a.dy, a.eps, a.g, o);
+      interface_flux(fy, ayl, a.dy, a.eps, a.g, o);
+      double ynew[14], yprev[14];
       ifo_to_array(o, ynew);
-      assemble<1>(yprev, ynew, eta, H1, H2, a.g, a.idy, R);
 #pragma unroll
-      for (int k = 0; k < 14; ++k) yprev[k] = ynew[k];
+      for (int k = 0; k < 14; ++k) { yprev[k] = sy[k][lane]; sy[k][lane] = ynew[k]; }
+      assemble<1>(yprev, ynew, eta, H1, H2, a.g, a.idy, R);
     }
 
     if (col_out) {
@@ -271,12 +280,13 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
           a.out[q] = R[0]; a.out[n + q] = R[1]; a.out[2 * n + q] = R[3]; a.out[3 * n + q] = R[4];
         }
       } else {
-        // limited derivatives of this stage's state at the node (Sec. 2.2)
+        // limited derivatives of this stage's state at the node (Sec. 2.2); the x-neighbours'
+        // surface, momenta and x-derivatives are the first six slots of their shared fluxes
         double Dm[6];
         if (a.limiter) {
-          limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], sx[S_ETA][lb], sx[S_M][lb], sx[S_W][lb],
-                      sx[S_ETA][ld], sx[S_M][ld], sx[S_W][ld], sx[S_H1][lb], sx[S_M1][lb], sx[S_W1][lb],
-                      sx[S_H1][ld], sx[S_M1][ld], sx[S_W1][ld], a.dx, a.idx, a.eps, a.g, Dm);
+          limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], sn[0][lb], sn[1][lb], sn[2][lb], sn[0][ld], sn[1][ld],
+                      sn[2][ld], sn[3][lb], sn[4][lb], sn[5][lb], sn[3][ld], sn[4][ld], sn[5][ld], a.dx, a.idx,
+                      a.eps, a.g, Dm);
           if (DIM == 2) {
             double o3[3];
             limit_frame(w0[S_ETA], w0[S_W], w0[S_M], w0[S_B], wm1[S_ETA], wm1[S_W], wm1[S_M], wp1[S_ETA],
@@ -434,6 +444,7 @@ struct swe_hweno_ctx {
   hipGraphExec_t g1 = nullptr, g8 = nullptr;
   const double* g_state = nullptr;
   int g_tend = 0;
+  int rows = ROWS_DEFAULT;  // rows marched per wave (2D), chosen at init
   // kernel timing: event pairs around stage kernels (slot 0 = bare right-hand side, 1..3 = stages)
   bool timing = false;
   struct Pending { hipEvent_t a, b; int slot; };
@@ -480,12 +491,13 @@ KArgs base_args(const swe_hweno_ctx* c) {
   a.dy = c->p.dim == 2 ? (c->p.y1 - c->p.y0) / c->p.ny : 1.0;
   a.idx = 1.0 / a.dx; a.idy = 1.0 / a.dy;
   a.g = c->p.g; a.eps = c->p.eps;
+  a.rows = c->rows;
   return a;
 }
 
 dim3 stage_grid(const swe_hweno_ctx* c) {
   const unsigned gx = (unsigned)((c->p.nx + OUT_COLS - 1) / OUT_COLS);
-  const unsigned gy = c->p.dim == 2 ? (unsigned)((c->p.ny + ROWS - 1) / ROWS) : 1u;
+  const unsigned gy = c->p.dim == 2 ? (unsigned)((c->p.ny + c->rows - 1) / c->rows) : 1u;
   return dim3(gx, gy, 1);
 }
 
@@ -571,6 +583,27 @@ void enqueue_step(swe_hweno_ctx* c, double* state, int use_tend, hipStream_t s) 
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SWE_OK : SWE_EHIP; }
 
+// Rows marched per wave in 2D: the wave count gx * ceil(ny / rows) should fill whole rounds of
+// the resident-wave slots (one fused-stage wave per SIMD), while each march repays its start-up
+// (four window rows and one extra y-interface, about two rows of work). Cost model: rounds *
+// (rows + 2); ties go to more rows. SWE_HWENO_ROWS overrides the choice.
+int choose_rows(int nx, int ny, int slots) {
+  if (const char* e = std::getenv("SWE_HWENO_ROWS")) {
+    const int r = std::atoi(e);
+    if (r >= 1 && r <= 4096) return r;
+  }
+  const long gx = (nx + OUT_COLS - 1) / OUT_COLS;
+  int best = ROWS_DEFAULT;
+  double best_cost = 1e300;
+  for (int r = 8; r <= 128; ++r) {
+    const long waves = gx * ((ny + r - 1) / r);
+    const long rounds = (waves + slots - 1) / slots;
+    const double cost = (double)rounds * (double)(std::min(r, ny) + 2);
+    if (cost < best_cost * (1 - 1e-12)) { best_cost = cost; best = r; }
+  }
+  return best;
+}
+
 int take_device_error(swe_hweno_ctx* c) {
   int e = 0;
   if (hipMemcpyAsync(&e, &c->sc->err, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
@@ -609,7 +642,14 @@ int swe_hweno_abi_version(void) { return SWE_HWENO_ABI_VERSION; }
 int swe_hweno_tile(int* cols_per_wave, int* rows_per_wave) {
   if (!cols_per_wave || !rows_per_wave) return SWE_EINVAL;
   *cols_per_wave = OUT_COLS;
-  *rows_per_wave = ROWS;
+  *rows_per_wave = ROWS_DEFAULT;
+  return SWE_OK;
+}
+
+int swe_hweno_ctx_tile(const swe_hweno_ctx* c, int* cols_per_wave, int* rows_per_wave) {
+  if (!c || !cols_per_wave || !rows_per_wave) return SWE_EINVAL;
+  *cols_per_wave = OUT_COLS;
+  *rows_per_wave = c->rows;
   return SWE_OK;
 }
 
@@ -646,6 +686,13 @@ int swe_hweno_init(const swe_hweno_params* p, const double* b, const double* bx,
   if (!ok) { swe_hweno_destroy(c); return SWE_ENOMEM; }
   c->bx = c->b + c->n;
   c->by = c->b + 2 * c->n;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || cus <= 0)
+      cus = 256;
+    c->rows = choose_rows(p->nx, p->dim == 2 ? p->ny : 1, 4 * cus);
+  }
   ok = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipMemcpyAsync(c->b, b, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
   ok = ok && hipMemcpyAsync(c->bx, bx, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;

@@ -105,6 +105,12 @@ class Solver:
         _lib.check(self._L.swe_hweno_get_timing(self._ctx, ms, n), "swe_hweno_get_timing")
         return {k: (ms[i], n[i]) for i, k in enumerate(("rhs", "stage1", "stage2", "stage3"))}
 
+    def tile(self):
+        """(output columns per wavefront, rows per wavefront march) of this context."""
+        c, r = ctypes.c_int(), ctypes.c_int()
+        _lib.check(self._L.swe_hweno_ctx_tile(self._ctx, ctypes.byref(c), ctypes.byref(r)), "swe_hweno_ctx_tile")
+        return c.value, r.value
+
     def sync(self):
         _lib.check(self._L.swe_hweno_sync(self._ctx), "swe_hweno_sync")
 

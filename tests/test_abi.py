@@ -86,6 +86,7 @@ def test_null_arguments_rejected(L):
     assert L.swe_hweno_tile(None, None) == -1
     assert L.swe_hweno_set_timing(None, 1) == -1
     assert L.swe_hweno_get_timing(None, None, None) == -1
+    assert L.swe_hweno_ctx_tile(None, None, None) == -1
 
 
 def test_product_path_has_no_cpu_fallback():
