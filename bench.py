@@ -13,7 +13,7 @@ roofline = the fused stage kernel against the FP64 vector peak, with the algorit
 node counted by the oracle (right-hand side + limiter) plus the Runge-Kutta combination; its
 duration comes from HIP events around every stage launch inside the timed region.
 cpu_baseline = the oracle (plain C++ FP64, OpenMP over rows) timed on this host on a bounded
-sample: one SSP-RK3 step of the same workload at --cpu-n x --cpu-n nodes.
+sample: --cpu-steps SSP-RK3 steps of the same 4096^2 state.
 """
 from __future__ import annotations
 
@@ -62,23 +62,23 @@ def flop_counts():
     return d["rhs_flops_per_node"], d["limiter_flops_per_node"]
 
 
-def cpu_baseline(n):
-    import numpy as np  # noqa: F401
-
+def cpu_baseline(pr, steps):
+    """The oracle on this host: `steps` SSP-RK3 steps of the same workload state."""
     import oracle
-    from paper_2208_01260_amd import inputs
 
     oracle.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     oracle.set_threads(threads)
-    pr = inputs.c3_2d(n)
     p = oracle.params_of(pr)
+    state = pr.state
     t0 = time.perf_counter()
-    oracle.step(p, pr.state, pr.b, pr.bx, pr.by)
+    for _ in range(steps):
+        state, _dt = oracle.step(p, state, pr.b, pr.bx, pr.by)
     dt = time.perf_counter() - t0
-    return {"value": 3.0 * pr.cells / dt, "unit": "cell-RHS/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"one SSP-RK3 step (3 right-hand sides, limiter, update) of the dam-break workload at "
-                      f"{n}x{n} nodes, {dt:.1f} s"}
+    return {"value": 3.0 * pr.cells * steps / dt, "unit": "cell-RHS/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 step(s) (3 right-hand sides, limiter, update each) of the same "
+                      f"{pr.nx}x{pr.ny} dam-break state, {dt:.1f} s wall on {oracle.get_threads()} threads"}
 
 
 def main():
@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=4096, help="grid nodes per direction")
-    ap.add_argument("--cpu-n", type=int, default=2048, help="oracle sample size (nodes per direction)")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle sample: steps of the same workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
@@ -175,11 +175,13 @@ def main():
                   "hbm_GBs": RHS_BYTES * cells / (rhs_ms * 1e-3) / 1e9}
 
     if args.copy_calib:
+        # plain streaming kernels of known size for PMC calibration: a fill (writes N bytes) and
+        # an elementwise b = a + 1 (reads N bytes, writes N bytes)
         n = args.copy_calib * (1 << 20) // 8
         a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.add(a, 1.0, out=b)
         torch.cuda.synchronize()
 
     line = {
@@ -196,7 +198,7 @@ def main():
     }
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.cpu_n)
+        line["cpu_baseline"] = cpu_baseline(pr, args.cpu_steps)
     s.close()
     print(json.dumps(line), flush=True)
 
