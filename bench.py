@@ -81,6 +81,48 @@ def cpu_baseline(pr, steps):
                       f"{pr.nx}x{pr.ny} dam-break state, {dt:.1f} s wall on {oracle.get_threads()} threads"}
 
 
+def batched(args, torch):
+    """Batched forward solver: `count` independent instances of uneven sizes (64..512 nodes per
+    side, seeded bottoms and Gaussian humps, reflective walls), every stage one launch over all
+    instances' tiles, against the same instances advanced one plain context after another."""
+    from paper_2208_01260_amd import inputs
+    from paper_2208_01260_amd.solver import Batch, Solver
+
+    probs = inputs.c4_batch(args.batch_count)
+    cells = sum(p.nx * p.ny for p in probs)
+    with Batch(probs) as bt:
+        rows = bt.autotune()
+        bt.run(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.run(args.batch_steps)
+        torch.cuda.synchronize()
+        wall_b = time.perf_counter() - t0
+    # plain contexts, one instance after another (graph replay each), on a subset that keeps
+    # this leg short; the rate is per cell-step so the subset size does not matter
+    sub = probs[: max(1, min(len(probs), args.batch_loop))]
+    sub_cells = sum(p.nx * p.ny for p in sub)
+    ctxs = [(Solver.from_problem(p), torch.from_numpy(p.state).cuda().contiguous()) for p in sub]
+    for s, st in ctxs:
+        s.run(st, nsteps=args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, st in ctxs:
+        s.run(st, nsteps=args.batch_steps)
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t0
+    for s, _ in ctxs:
+        s.close()
+    rate_b = cells * args.batch_steps / wall_b
+    rate_p = sub_cells * args.batch_steps / wall_p
+    print(f"[bench] batch: {len(probs)} instances, {cells} cells, {rate_b:.3e} cell-steps/s "
+          f"(plain loop {rate_p:.3e}, rows {rows})", file=sys.stderr, flush=True)
+    return {"instances": len(probs), "cells": cells, "steps": args.batch_steps, "rows_per_wave": rows,
+            "ms_per_step": wall_b * 1e3 / args.batch_steps, "cell_steps_per_s": rate_b,
+            "cell_rhs_per_s": 3.0 * rate_b, "plain_loop_instances": len(sub),
+            "plain_loop_cell_steps_per_s": rate_p, "speedup_vs_plain_loop": rate_b / rate_p}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +131,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="grid nodes per direction")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle sample: steps of the same workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched leg (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-loop", type=int, default=64, help="instances timed one by one for comparison")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -196,6 +241,8 @@ def main():
         "tile": {"cols_per_wave": tile[0], "rows_per_wave": tile[1]},
         "cell_steps_per_s": cells * args.steps / wall,
     }
+    if args.batch_count > 0:
+        line["batched"] = batched(args, torch)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_steps)

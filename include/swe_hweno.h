@@ -135,6 +135,55 @@ int swe_hweno_tile(int* cols_per_wave, int* rows_per_wave);
  * compute-unit count (environment variable SWE_HWENO_ROWS overrides). Host-only. */
 int swe_hweno_ctx_tile(const swe_hweno_ctx* ctx, int* cols_per_wave, int* rows_per_wave);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched solver: many independent 2D instances of uneven sizes, each with its own bottom,
+ * state, Lax-Friedrichs speeds and CFL time step, advanced together. Every stage of every
+ * instance is one launch of the fused stage kernel over all instances' tiles (a per-wavefront
+ * table maps each wavefront to its instance and tile), and the steps of a run are replayed
+ * from captured HIP graphs of at most 16 steps. Each step is the one swe_hweno_step takes (the
+ * scheme of Sec. 2 and 3 of the paper: SSP-RK3 stages, each a full right-hand side, limiter and
+ * update). Each instance's result is bitwise the result of the plain solver on the same
+ * instance with the same rows per march: the batch tiling changes no arithmetic.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct swe_hweno_batch swe_hweno_batch; /* opaque, owned by the library */
+
+typedef struct {
+  int nx, ny;               /* nodes, >= 4 each */
+  double x0, x1, y0, y1;    /* domain */
+  int bc_x, bc_y;           /* SWE_BC_PERIODIC or SWE_BC_REFLECTIVE */
+  const double* b;          /* DEVICE planes of nx*ny: bottom and its x-, y-derivatives (copied at init) */
+  const double* bx;
+  const double* by;
+  double* state;            /* DEVICE, 9 planes of nx*ny, caller-owned; advanced in place by batch_run */
+} swe_hweno_instance;
+
+/* Create a batch of `count` (1..65535) instances. From `common` only g, cfl, eps, flags,
+ * fixed_dt, alpha_x, alpha_y are used (dim must be 2; nx, ny, domain and bc are per instance).
+ * The instance array is read during the call only; the state pointers are kept and must stay
+ * valid while the batch exists. */
+int swe_hweno_batch_init(const swe_hweno_params* common, const swe_hweno_instance* inst, int count, void* stream,
+                         swe_hweno_batch** out);
+
+/* nsteps SSP-RK3 steps of every instance (each at its own CFL step; no end time), replayed from
+ * captured graphs. Every run starts each instance's clock at 0 and its speeds from its current
+ * state; t_out (HOST array of count, nullable) receives the time each instance advanced.
+ * Synchronises. An instance whose time step turns non-finite (or whose depth turns
+ * non-positive) stops where it is while the others go on, and the call returns SWE_ENONFINITE
+ * (SWE_EDRY); nsteps < 1 is SWE_EINVAL. */
+int swe_hweno_batch_run(swe_hweno_batch* bt, int nsteps, double* t_out);
+
+/* Rows per wavefront march of the batch kernels (>= 1); swe_hweno_batch_autotune times the
+ * fused kernel on the batch's own data for a set of candidates (into scratch buffers, the
+ * states are not touched), keeps the fastest and returns it. */
+int swe_hweno_batch_set_rows(swe_hweno_batch* bt, int rows);
+int swe_hweno_batch_autotune(swe_hweno_batch* bt, int* rows_out);
+
+/* Synchronise and report (and clear) device-detected errors of any instance. */
+int swe_hweno_batch_sync(swe_hweno_batch* bt);
+
+/* Free the batch (synchronises first). NULL is a no-op. */
+void swe_hweno_batch_destroy(swe_hweno_batch* bt);
+
 #ifdef __cplusplus
 }
 #endif

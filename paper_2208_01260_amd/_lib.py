@@ -21,7 +21,9 @@ ABI_VERSION = 1
 # every symbol include/swe_hweno.h declares
 EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alpha", "swe_hweno_step",
            "swe_hweno_run", "swe_hweno_sync", "swe_hweno_destroy", "swe_hweno_strerror", "swe_hweno_abi_version",
-           "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing", "swe_hweno_ctx_tile")
+           "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing", "swe_hweno_ctx_tile",
+           "swe_hweno_batch_init", "swe_hweno_batch_run", "swe_hweno_batch_set_rows", "swe_hweno_batch_autotune",
+           "swe_hweno_batch_sync", "swe_hweno_batch_destroy")
 
 
 class SweError(RuntimeError):
@@ -37,6 +39,15 @@ class Params(ctypes.Structure):
         ("g", ctypes.c_double), ("cfl", ctypes.c_double), ("eps", ctypes.c_double),
         ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("flags", ctypes.c_int),
         ("fixed_dt", ctypes.c_double), ("alpha_x", ctypes.c_double), ("alpha_y", ctypes.c_double),
+    ]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+        ("b", ctypes.c_void_p), ("bx", ctypes.c_void_p), ("by", ctypes.c_void_p), ("state", ctypes.c_void_p),
     ]
 
 
@@ -66,6 +77,12 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_tile": (I, [ctypes.POINTER(I), ctypes.POINTER(I)]),
         "swe_hweno_set_timing": (I, [vp, I]),
         "swe_hweno_ctx_tile": (I, [vp, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "swe_hweno_batch_init": (I, [P, ctypes.POINTER(Instance), I, vp, ctypes.POINTER(vp)]),
+        "swe_hweno_batch_run": (I, [vp, I, ctypes.POINTER(D)]),
+        "swe_hweno_batch_set_rows": (I, [vp, I]),
+        "swe_hweno_batch_autotune": (I, [vp, ctypes.POINTER(I)]),
+        "swe_hweno_batch_sync": (I, [vp]),
+        "swe_hweno_batch_destroy": (None, [vp]),
         "swe_hweno_get_timing": (I, [vp, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
     }
     for name, (res, args) in sig.items():

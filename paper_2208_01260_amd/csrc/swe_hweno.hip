@@ -67,6 +67,13 @@ struct KArgs {
 
 __device__ __forceinline__ double bits2d(unsigned long long u) { return __longlong_as_double((long long)u); }
 
+// CFL time step from the Lax-Friedrichs speeds, rounded operation by operation (no contraction)
+// so that every kernel that computes it gets the same bits.
+__device__ __noinline__ double cfl_step(int dim, double cfl, double ax, double ay, double dx, double dy) {
+#pragma clang fp contract(off)
+  return dim == 2 ? cfl / (ax / dx + ay / dy) : cfl / (ax / dx);
+}
+
 // Fold an index into [0, n): periodic wrap or mirror about the wall face (one fold suffices for
 // the stencil halos; indices of halo lanes farther out are clamped, their results are unused).
 __device__ __forceinline__ int fold(int i, int n, int bc, bool& refl) {
@@ -176,15 +183,16 @@ __device__ __forceinline__ void flush_speeds(const KArgs& a, double ax, double a
 }
 
 // --------------------------------------------------------------------------- the fused stage
+// One wavefront's tile: output columns [tx*60, tx*60+60) of rows [ty*rows, ty*rows+rows).
 template <int DIM, int MODE>
-__global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
+__device__ __forceinline__ void stage_tile(const KArgs& a, int tx, int ty) {
   if (MODE != MODE_RHS && a.sc->active == 0) return;
   __shared__ double sn[NNODE][WAVE];  // x-frame fluxes of the current row, one node per lane
   __shared__ double sf[14][WAVE];     // x-interface quantities (lane l: interface left of its column)
   __shared__ double sy[14][WAVE];     // y-interface quantities of the previous row (own lane)
   const int lane = threadIdx.x;
-  const int c = blockIdx.x * OUT_COLS - 2 + lane;  // this lane's column
-  const int r0 = DIM == 2 ? blockIdx.y * a.rows : 0;
+  const int c = tx * OUT_COLS - 2 + lane;  // this lane's column
+  const int r0 = DIM == 2 ? ty * a.rows : 0;
   const int r1 = DIM == 2 ? min(r0 + a.rows, a.ny) : 1;
   const bool col_out = lane >= 2 && lane < WAVE - 2 && c < a.nx;
   const int cq = col_out ? c : 0;  // a column that is always inside the grid
@@ -339,6 +347,11 @@ __global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
   if (MODE != MODE_RHS) flush_speeds(a, amx, amy, err);
 }
 
+template <int DIM, int MODE>
+__global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
+  stage_tile<DIM, MODE>(a, blockIdx.x, blockIdx.y);
+}
+
 // --------------------------------------------------------------------------- small kernels
 // Lax-Friedrichs speeds of a state (grid-stride), max-reduced into out[2].
 template <int DIM>
@@ -381,7 +394,7 @@ __global__ void k_prologue(DevScal* s, int dim, int fixed_dt, double fdt, double
   s->a_n[0] = s->a_next[0];
   s->a_n[1] = s->a_next[1];
   const double ax = bits2d(s->a_n[0]), ay = bits2d(s->a_n[1]);
-  double dt = fixed_dt ? fdt : (dim == 2 ? cfl / (ax / dx + ay / dy) : cfl / (ax / dx));
+  double dt = fixed_dt ? fdt : cfl_step(dim, cfl, ax, ay, dx, dy);
   int active = 1;
   if (use_tend) {
     if (!(s->t < s->t_end)) { active = 0; dt = 0.0; }
@@ -859,3 +872,5 @@ int swe_hweno_sync(swe_hweno_ctx* c) {
 }
 
 }  // extern "C"
+
+#include "swe_hweno_batch.inc"

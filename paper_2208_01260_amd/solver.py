@@ -136,3 +136,79 @@ def tile():
     c, r = ctypes.c_int(), ctypes.c_int()
     _lib.check(_lib.lib().swe_hweno_tile(ctypes.byref(c), ctypes.byref(r)))
     return c.value, r.value
+
+
+class Batch:
+    """Many independent 2D instances advanced together (swe_hweno_batch_*) on the current CUDA
+    stream. `problems` are paper_2208_01260_amd.inputs.Problem objects sharing g, cfl and eps; each
+    one's state is copied to the device into `self.states[i]` (shape (9, ny, nx)), unless `states`
+    gives the device tensors to advance in place. The bottoms are copied by the library."""
+
+    def __init__(self, problems, states=None, flags=0, fixed_dt=0.0, alpha=(0.0, 0.0), device="cuda", stream=None):
+        L = _lib.lib()
+        if not problems:
+            raise ValueError("a batch needs at least one instance")
+        g, cfl, eps = problems[0].g, problems[0].cfl, problems[0].eps
+        t = lambda a: torch.from_numpy(a).to(device=device, dtype=torch.float64).contiguous()
+        self.states = list(states) if states is not None else [t(pr.state) for pr in problems]
+        arr = (_lib.Instance * len(problems))()
+        keep = []
+        for i, pr in enumerate(problems):
+            if pr.dim != 2 or (pr.g, pr.cfl, pr.eps) != (g, cfl, eps):
+                raise ValueError("batched instances are 2D and share g, cfl and eps")
+            st = self.states[i]
+            ptr = _dev(st, f"states[{i}]")
+            if tuple(st.shape) != (9, pr.ny, pr.nx):
+                raise ValueError(f"states[{i}] must have shape {(9, pr.ny, pr.nx)}")
+            b, bx, by = t(pr.b), t(pr.bx), t(pr.by)
+            keep += [b, bx, by]
+            it = arr[i]
+            it.nx, it.ny = pr.nx, pr.ny
+            it.x0, it.x1, it.y0, it.y1 = [float(v) for v in pr.domain]
+            it.bc_x, it.bc_y = int(pr.bc[0]), int(pr.bc[1])
+            it.b, it.bx, it.by, it.state = b.data_ptr(), bx.data_ptr(), by.data_ptr(), ptr
+        p = _lib.Params()
+        p.dim, p.nx, p.ny = 2, 4, 4
+        p.x0, p.x1, p.y0, p.y1 = 0.0, 1.0, 0.0, 1.0
+        p.g, p.cfl, p.eps, p.flags = g, cfl, eps, int(flags)
+        p.fixed_dt, p.alpha_x, p.alpha_y = float(fixed_dt), float(alpha[0]), float(alpha[1])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _lib.check(L.swe_hweno_batch_init(ctypes.byref(p), arr, len(problems), ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)), "swe_hweno_batch_init")
+        self._h, self._L, self.count = h, L, len(problems)
+        self.cells = sum(pr.nx * pr.ny for pr in problems)
+
+    def run(self, nsteps):
+        """nsteps steps of every instance; returns the time each advanced."""
+        t = (ctypes.c_double * self.count)()
+        _lib.check(self._L.swe_hweno_batch_run(self._h, int(nsteps), t), "swe_hweno_batch_run")
+        return list(t)
+
+    def set_rows(self, rows):
+        _lib.check(self._L.swe_hweno_batch_set_rows(self._h, int(rows)), "swe_hweno_batch_set_rows")
+
+    def autotune(self):
+        r = ctypes.c_int()
+        _lib.check(self._L.swe_hweno_batch_autotune(self._h, ctypes.byref(r)), "swe_hweno_batch_autotune")
+        return r.value
+
+    def sync(self):
+        _lib.check(self._L.swe_hweno_batch_sync(self._h), "swe_hweno_batch_sync")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.swe_hweno_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -87,6 +87,30 @@ def test_null_arguments_rejected(L):
     assert L.swe_hweno_set_timing(None, 1) == -1
     assert L.swe_hweno_get_timing(None, None, None) == -1
     assert L.swe_hweno_ctx_tile(None, None, None) == -1
+    assert L.swe_hweno_batch_run(None, 1, None) == -1
+    assert L.swe_hweno_batch_set_rows(None, 8) == -1
+    assert L.swe_hweno_batch_autotune(None, None) == -1
+    assert L.swe_hweno_batch_sync(None) == -1
+    L.swe_hweno_batch_destroy(None)
+
+
+def test_batch_init_rejects_bad_arguments(L):
+    from paper_2208_01260_amd import _lib
+
+    p = _params()
+    arr = (_lib.Instance * 2)()
+    for it in arr:
+        it.nx, it.ny, it.x0, it.x1, it.y0, it.y1 = 16, 16, 0.0, 1.0, 0.0, 1.0
+        it.b = it.bx = it.by = it.state = 0x1000  # never dereferenced: validation fails first
+    h = ctypes.c_void_p(7)
+    assert L.swe_hweno_batch_init(ctypes.byref(p), arr, 0, None, ctypes.byref(h)) == -1 and h.value is None
+    arr[1].ny = 3
+    assert L.swe_hweno_batch_init(ctypes.byref(p), arr, 2, None, ctypes.byref(h)) == -1
+    arr[1].ny = 16
+    arr[0].state = None
+    assert L.swe_hweno_batch_init(ctypes.byref(p), arr, 2, None, ctypes.byref(h)) == -1
+    p1 = _params(dim=1, ny=1)
+    assert L.swe_hweno_batch_init(ctypes.byref(p1), arr, 2, None, ctypes.byref(h)) == -1
 
 
 def test_product_path_has_no_cpu_fallback():
