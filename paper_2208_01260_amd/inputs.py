@@ -287,6 +287,36 @@ def paper_perturbed_1d(pulse=0.2, n=200):
                  eps=1e-10 if pulse < 0.01 else 1e-6)
 
 
+def paper_wavy_1d(n=200):
+    """Ex. 4.4: wavy bottom b = 0.3 cos^30(pi/2 (x-1)) on [0, 2] (0 elsewhere) in [-10, 10];
+    h + b = 2, u = 1 for x <= 1 and h + b = 0.35, u = 0 beyond; t = 1. The paper states no
+    boundary condition: reflective walls here (no wave reaches the region the paper plots by t = 1)."""
+    def bfun(x):
+        xr = x.real
+        return np.where((xr >= 0.0) & (xr <= 2.0), 0.3 * np.cos(0.5 * np.pi * (x - 1.0)) ** 30, 0.0 * x)
+
+    def eta(x):
+        return np.where(x.real <= 1.0, 2.0, 0.35) + 0.0 * x
+
+    def m(x):
+        return np.where(x.real <= 1.0, 2.0 - bfun(x), 0.0 * x)
+
+    return _mk1d("paper_wavy_1d", n, (-10.0, 10.0), REFLECTIVE, bfun, eta, m, t_end=1.0)
+
+
+def paper_rect_dam_1d(n=200, t_end=15.0):
+    """Ex. 4.5: dam break over a rectangular hump b = 8 on |x - 750| <= 1500/8 in (0, 1500);
+    h + b = 20 for x <= 750, 15 beyond, u = 0; t = 15 and 60. Reflective walls (the paper states
+    none; by t = 15 no wave has reached them)."""
+    def bfun(x):
+        return np.where(np.abs(x.real - 750.0) <= 1500.0 / 8.0, 8.0, 0.0) + 0.0 * x
+
+    def eta(x):
+        return np.where(x.real <= 750.0, 20.0, 15.0) + 0.0 * x
+
+    return _mk1d("paper_rect_dam_1d", n, (0.0, 1500.0), REFLECTIVE, bfun, eta, _zero, t_end=t_end)
+
+
 def paper_accuracy_2d(n):
     """Ex. 4.6: b = sin 2 pi x + sin 2 pi y, periodic on [0,1]^2, t = 0.05."""
     def bfun(x, y):
@@ -317,8 +347,17 @@ def paper_lake_2d(n=200):
                  t_end=0.1)
 
 
-def paper_perturbed_2d(nx=200, ny=100):
-    """Ex. 4.8: b = 0.8 exp(-5(x-0.9)^2 - 50(y-0.5)^2) on [0,2]x[0,1], h = 1 - b (+0.01 on 0.05<x<0.15)."""
+def paper_perturbed_2d(nx=200, ny=100, pad=0.0):
+    """Ex. 4.8: b = 0.8 exp(-5(x-0.9)^2 - 50(y-0.5)^2) on [0,2]x[0,1], h = 1 - b (+0.01 on 0.05<x<0.15).
+
+    The paper gives no boundary condition; its comparison ranges are those of a run whose waves
+    leave the domain. pad > 0 extends the domain by pad on both sides in x (same dx, reflective
+    walls farther out) so that the walls' reflections re-enter [0, 2] only after t = 2 pad / sqrt(g);
+    extra["window_x"] is the paper's x-range."""
+    dx = 2.0 / nx
+    extra = int(round(pad / dx))
+    dom = (-extra * dx, 2.0 + extra * dx, 0.0, 1.0)
+
     def bfun(x, y):
         return 0.8 * np.exp(-5.0 * (x - 0.9) ** 2 - 50.0 * (y - 0.5) ** 2)
 
@@ -326,8 +365,10 @@ def paper_perturbed_2d(nx=200, ny=100):
         xr = x.real
         return 1.0 + np.where((xr >= 0.05) & (xr <= 0.15), 0.01, 0.0) + 0.0 * x
 
-    return _mk2d("paper_perturbed_2d", nx, ny, (0.0, 2.0, 0.0, 1.0), (REFLECTIVE, REFLECTIVE), bfun, eta,
-                 _zero2, _zero2, t_end=0.12)
+    pr = _mk2d("paper_perturbed_2d", nx + 2 * extra, ny, dom, (REFLECTIVE, REFLECTIVE), bfun, eta,
+               _zero2, _zero2, t_end=0.12)
+    pr.extra["window_x"] = (0.0, 2.0)
+    return pr
 
 
 def paper_dam_2d(n=200):
