@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "2D HWENO RHS cell-updates/s FP64 (% roofline); batched & adjoint vs plain"
 PEAK_FP64 = 78.6e12   # FP64 vector FLOP/s (FMA = 2), MI355X
+PEAK_FP32 = 157.3e12  # FP32 vector FLOP/s (FMA = 2), MI355X
 PEAK_HBM = 8.0e12     # B/s
 RK_FLOPS = (18 + 45 + 45) / 3.0   # per node per stage: U + dt R; (3a + b)/4; (a + 2b)/3, 9 fields
 SPEED_FLOPS = 8                   # |u| + c, |v| + c per node (h, 1/h, 2 products, sqrt, 2 adds)
@@ -81,6 +82,39 @@ def cpu_baseline(pr, steps):
                       f"{pr.nx}x{pr.ny} dam-break state, {dt:.1f} s wall on {oracle.get_threads()} threads"}
 
 
+def single_precision(args, torch, pr, f_rhs):
+    """The FP32 variant on the same workload: the bare right-hand side kernel (alpha given) and
+    graph-replayed steps."""
+    from paper_2208_01260_amd.solver import Solver
+
+    cells = pr.cells
+    st0 = torch.from_numpy(pr.state).to(device="cuda:0", dtype=torch.float32).contiguous()
+    with Solver.from_problem(pr, dtype=torch.float32) as s:
+        st = st0.clone()
+        ax, ay = s.alpha(st)
+        out = torch.empty_like(st)
+        s.set_timing(True)
+        for _ in range(args.warmup):
+            s.rhs(st, out, alpha=(ax, ay))
+        s.set_timing(True)
+        for _ in range(args.steps):
+            s.rhs(st, out, alpha=(ax, ay))
+        tim = s.get_timing()
+        rhs_ms = tim["rhs"][0] / tim["rhs"][1]
+        s.set_timing(False)
+        s.run(st, nsteps=args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(st, nsteps=args.steps)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(f"[bench] fp32: rhs {rhs_ms:.3f} ms, step {step_ms:.3f} ms", file=sys.stderr, flush=True)
+    return {"rhs_avg_launch_ms": rhs_ms, "rhs_cell_updates_per_s": cells / (rhs_ms * 1e-3),
+            "rhs_tflops": f_rhs * cells / (rhs_ms * 1e-3) / 1e12,
+            "rhs_frac_fp32_peak": f_rhs * cells / (rhs_ms * 1e-3) / PEAK_FP32,
+            "ms_per_step": step_ms, "cell_rhs_per_s": 3.0 * cells / (step_ms * 1e-3)}
+
+
 def batched(args, torch):
     """Batched forward solver: `count` independent instances of uneven sizes (64..512 nodes per
     side, seeded bottoms and Gaussian humps, reflective walls), every stage one launch over all
@@ -131,6 +165,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="grid nodes per direction")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle sample: steps of the same workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the single-precision leg")
     ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-loop", type=int, default=64, help="instances timed one by one for comparison")
@@ -241,12 +276,14 @@ def main():
         "tile": {"cols_per_wave": tile[0], "rows_per_wave": tile[1]},
         "cell_steps_per_s": cells * args.steps / wall,
     }
+    s.close()
+    if not args.no_fp32:
+        line["fp32"] = single_precision(args, torch, pr, f_rhs)
     if args.batch_count > 0:
         line["batched"] = batched(args, torch)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_steps)
-    s.close()
     print(json.dumps(line), flush=True)
 
 

@@ -3,7 +3,7 @@
  * finite-difference Hermite WENO scheme for the shallow water equations in pre-balanced form
  * (Zhao & Zhang, arXiv 2208.01260).
  *
- * What the library computes (FP64 throughout):
+ * What the library computes (in FP64; the _f32 entry points run the same scheme in FP32):
  *   - the semi-discrete right-hand side of Sec. 2.1 (1D, eq. (2.8)) and Sec. 3 (2D, eq. (3.8)):
  *     Lax-Friedrichs split (eq. (2.4)), characteristic-wise nonlinear HWENO reconstruction of the
  *     original-equation fluxes (eqs. (2.5), (2.7)), linear Hermite derivative fluxes (eq. (2.6)),
@@ -126,6 +126,23 @@ int swe_hweno_abi_version(void);
  * the summed milliseconds and launch counts of [bare right-hand side, stage 1, stage 2, stage 3]. */
 int swe_hweno_set_timing(swe_hweno_ctx* ctx, int on);
 int swe_hweno_get_timing(swe_hweno_ctx* ctx, double* ms, long long* launches);
+
+/* ------------------------------------------------------------------------------------------
+ * Single precision. The same scheme, kernels and launch shapes with every array and all device
+ * arithmetic in FP32 (the paper's lake-at-rest tables report single, double and quadruple
+ * precision runs, Sec. 4, Tables 1-3). A context made by swe_hweno_init_f32 takes float planes
+ * (same layouts as above) and only the _f32 calls below plus the type-free ones (sync,
+ * destroy, timing, tile); an FP64 call on it, or an _f32 call on an FP64 context, returns
+ * SWE_EINVAL. Parameters, alpha and dt stay double on the host; the speeds are reduced in
+ * FP32 and dt is formed in FP64 from them.
+ * ------------------------------------------------------------------------------------------ */
+int swe_hweno_init_f32(const swe_hweno_params* params, const float* b, const float* bx, const float* by,
+                       void* stream, swe_hweno_ctx** out);
+int swe_hweno_rhs_f32(swe_hweno_ctx* ctx, const float* state, float* rhs, double alpha_x, double alpha_y);
+int swe_hweno_limit_f32(swe_hweno_ctx* ctx, const float* state, float* dmod);
+int swe_hweno_alpha_f32(swe_hweno_ctx* ctx, const float* state, double* alpha_host);
+int swe_hweno_step_f32(swe_hweno_ctx* ctx, float* state, double dt, double* dt_used);
+int swe_hweno_run_f32(swe_hweno_ctx* ctx, float* state, int nsteps, double t_end, double* t_out, int* steps_out);
 
 /* Dimensions of the fused stage kernel's tiles (columns of output per wavefront and the default
  * rows per wavefront march); for tests and benchmarks. Host-only, no HIP call. */

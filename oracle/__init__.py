@@ -66,6 +66,8 @@ def lib():
             "orc_step": (I, [P, _D, _D, _D, _D, Dd, _D]),
             "orc_run": (I, [P, _D, _D, _D, _D, I, Dd, _D, ctypes.POINTER(I)]),
             "orc_run_delta_f32": (I, [P, _D, _D, _D, _D, I, Dd, _D, _D, ctypes.POINTER(I)]),
+            "orc_rhs_f32": (I, [P, _D, _D, _D, _D, Dd, Dd, _D]),
+            "orc_run_f32": (I, [P, _D, _D, _D, _D, I, Dd, _D, ctypes.POINTER(I)]),
             "orc_run_delta_f64": (I, [P, _D, _D, _D, _D, I, Dd, _D, _D, ctypes.POINTER(I)]),
             "orc_run_delta_f128": (I, [P, _D, _D, _D, _D, I, Dd, _D, _D, ctypes.POINTER(I)]),
             "orc_count_rhs": (I, [P, _D, _D, _D, _D, Dd, Dd, ctypes.POINTER(ctypes.c_longlong)]),
@@ -164,6 +166,25 @@ def rhs(p, state, b, bx, by=None, alpha_x=-1.0, alpha_y=-1.0):
     out = np.empty_like(state)
     _check(lib().orc_rhs(ctypes.byref(p), _p(state), _p(b), _p(bx), _p(by), alpha_x, alpha_y, _p(out)))
     return out
+
+
+def rhs_f32(p, state, b, bx, by=None, alpha_x=-1.0, alpha_y=-1.0):
+    """The right-hand side computed by the single-precision scheme (inputs rounded to float)."""
+    state = _f64(state)
+    b, bx, by = _bottom(p, b, bx, by)
+    out = np.empty_like(state)
+    _check(lib().orc_rhs_f32(ctypes.byref(p), _p(state), _p(b), _p(bx), _p(by), alpha_x, alpha_y, _p(out)))
+    return out
+
+
+def run_f32(p, state, b, bx, by=None, nsteps=0, t_end=0.0):
+    """A run of the single-precision scheme; the final float state is returned widened."""
+    s = np.array(state, dtype=np.float64, copy=True)
+    b, bx, by = _bottom(p, b, bx, by)
+    t, k = ctypes.c_double(), ctypes.c_int()
+    _check(lib().orc_run_f32(ctypes.byref(p), _p(s), _p(b), _p(bx), _p(by), nsteps, t_end, ctypes.byref(t),
+                             ctypes.byref(k)))
+    return s, t.value, k.value
 
 
 def limit(p, state, b, bx, by=None):

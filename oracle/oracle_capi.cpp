@@ -161,6 +161,38 @@ int orc_run(const orc_params* p, double* state, const double* b, const double* b
   return s.run(state, nsteps, t_end, t_out, steps_out);
 }
 
+// The scheme run in single precision (Scheme<float>), inputs rounded to float, results widened
+// to double: the right-hand side (alpha_x < 0: alpha from the rounded state, in float) and a
+// run of the state in place.
+int orc_rhs_f32(const orc_params* p, const double* state, const double* b, const double* bx, const double* by,
+                double alpha_x, double alpha_y, double* rhs) {
+  Scheme<float> s;
+  int e = make(p, b, bx, by, s);
+  if (e) return e;
+  const size_t n = nodes(p), N = (size_t)nfields(p) * n;
+  std::vector<float> S = to_t<float>(state, N), R(N);
+  float ax = float(alpha_x), ay = float(alpha_y);
+  if (alpha_x < 0) {
+    s.alpha(S.data(), ax, ay);
+    if (s.err) return s.err;
+  }
+  s.rhs(S.data(), S.data() + (size_t)s.nu * n, ax, ay, R.data(), R.data() + (size_t)s.nu * n);
+  for (size_t q = 0; q < N; ++q) rhs[q] = double(R[q]);
+  return OK;
+}
+
+int orc_run_f32(const orc_params* p, double* state, const double* b, const double* bx, const double* by,
+                int nsteps, double t_end, double* t_out, int* steps_out) {
+  Scheme<float> s;
+  int e = make(p, b, bx, by, s);
+  if (e) return e;
+  const size_t N = (size_t)nfields(p) * nodes(p);
+  std::vector<float> S = to_t<float>(state, N);
+  e = s.run(S.data(), nsteps, t_end, t_out, steps_out);
+  for (size_t q = 0; q < N; ++q) state[q] = double(S[q]);
+  return e;
+}
+
 int orc_run_delta_f32(const orc_params* p, const double* state, const double* b, const double* bx, const double* by,
                       int nsteps, double t_end, double* delta, double* t_out, int* steps_out) {
   return run_delta<float>(p, state, b, bx, by, nsteps, t_end, delta, t_out, steps_out);

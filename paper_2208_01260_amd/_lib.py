@@ -23,7 +23,9 @@ EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alph
            "swe_hweno_run", "swe_hweno_sync", "swe_hweno_destroy", "swe_hweno_strerror", "swe_hweno_abi_version",
            "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing", "swe_hweno_ctx_tile",
            "swe_hweno_batch_init", "swe_hweno_batch_run", "swe_hweno_batch_set_rows", "swe_hweno_batch_autotune",
-           "swe_hweno_batch_sync", "swe_hweno_batch_destroy")
+           "swe_hweno_batch_sync", "swe_hweno_batch_destroy",
+           "swe_hweno_init_f32", "swe_hweno_rhs_f32", "swe_hweno_limit_f32", "swe_hweno_alpha_f32",
+           "swe_hweno_step_f32", "swe_hweno_run_f32")
 
 
 class SweError(RuntimeError):
@@ -70,6 +72,12 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_alpha": (I, [vp, dp, ctypes.POINTER(D)]),
         "swe_hweno_step": (I, [vp, dp, D, ctypes.POINTER(D)]),
         "swe_hweno_run": (I, [vp, dp, I, D, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "swe_hweno_init_f32": (I, [P, dp, dp, dp, vp, ctypes.POINTER(vp)]),
+        "swe_hweno_rhs_f32": (I, [vp, dp, dp, D, D]),
+        "swe_hweno_limit_f32": (I, [vp, dp, dp]),
+        "swe_hweno_alpha_f32": (I, [vp, dp, ctypes.POINTER(D)]),
+        "swe_hweno_step_f32": (I, [vp, dp, D, ctypes.POINTER(D)]),
+        "swe_hweno_run_f32": (I, [vp, dp, I, D, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "swe_hweno_sync": (I, [vp]),
         "swe_hweno_destroy": (None, [vp]),
         "swe_hweno_strerror": (ctypes.c_char_p, [I]),

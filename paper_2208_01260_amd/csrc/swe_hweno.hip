@@ -1,6 +1,7 @@
 // MI355X (gfx950) implementation of the C ABI in include/swe_hweno.h: the right-hand side of the
 // well-balanced fifth-order finite-difference HWENO scheme for the shallow water equations, its
-// derivative limiter and SSP-RK3 stages (Zhao & Zhang, arXiv 2208.01260), FP64.
+// derivative limiter and SSP-RK3 stages (Zhao & Zhang, arXiv 2208.01260), in FP64 or FP32 (the
+// same kernels instantiated for both types).
 //
 // Kernel design (one wavefront per workgroup):
 //   * k_stage is the whole stage of eq. (2.11) in one pass: each lane owns one grid column and
@@ -49,21 +50,27 @@ struct DevScal {
   int active, steps, err, pad1;
 };
 
+template <class T>
 struct KArgs {
-  const double* S;        // state whose right-hand side / stage is computed
-  const double* Sn;       // U^n at the start of the step (stages 1, 2)
-  const double* Dn;       // D^{n,mod} (stages 1, 2)
-  const double* b;
-  const double* bx;
-  const double* by;
-  double* out;            // right-hand side, or the next stage state
-  double* Dn_out;         // stage 0: D^{n,mod}
+  const T* S;             // state whose right-hand side / stage is computed
+  const T* Sn;            // U^n at the start of the step (stages 1, 2)
+  const T* Dn;            // D^{n,mod} (stages 1, 2)
+  const T* b;
+  const T* bx;
+  const T* by;
+  T* out;                 // right-hand side, or the next stage state
+  T* Dn_out;              // stage 0: D^{n,mod}
   const unsigned long long* a_in;  // Lax-Friedrichs speeds used
   unsigned long long* a_out;       // max-reduction of the output state's speeds
   DevScal* sc;
   int nx, ny, bcx, bcy, limiter, rows;
-  double dx, dy, idx, idy, g, eps;
+  T dx, dy, idx, idy, g, eps;
 };
+
+// Largest finite value of the arithmetic type.
+template <class T> __device__ __forceinline__ constexpr T big_value();
+template <> __device__ __forceinline__ constexpr double big_value<double>() { return DBL_MAX; }
+template <> __device__ __forceinline__ constexpr float big_value<float>() { return FLT_MAX; }
 
 __device__ __forceinline__ double bits2d(unsigned long long u) { return __longlong_as_double((long long)u); }
 
@@ -88,8 +95,8 @@ __device__ __forceinline__ int fold(int i, int n, int bc, bool& refl) {
 
 // Raw node record at (i, j) in the slots of hweno_device.hpp, ghost values by parity:
 // across an x-wall m, H1, W1, M2, B1 are odd; across a y-wall w, W1, H2, M2, B2 are odd.
-template <int DIM>
-__device__ __forceinline__ void load_rec(const KArgs& a, const double* __restrict__ S, int i, int j, double r[NREC]) {
+template <int DIM, class T>
+__device__ __forceinline__ void load_rec(const KArgs<T>& a, const T* __restrict__ S, int i, int j, T r[NREC]) {
   bool rx, ry = false;
   const int ii = fold(i, a.nx, a.bcx, rx);
   const int jj = DIM == 2 ? fold(j, a.ny, a.bcy, ry) : 0;
@@ -100,10 +107,10 @@ __device__ __forceinline__ void load_rec(const KArgs& a, const double* __restric
     for (int f = 0; f < 9; ++f) r[f] = S[f * n + q];
     r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = a.by[q];
   } else {
-    r[S_ETA] = S[q]; r[S_M] = S[n + q]; r[S_W] = 0.0;
-    r[S_H1] = S[2 * n + q]; r[S_M1] = S[3 * n + q]; r[S_W1] = 0.0;
-    r[S_H2] = 0.0; r[S_M2] = 0.0; r[S_W2] = 0.0;
-    r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = 0.0;
+    r[S_ETA] = S[q]; r[S_M] = S[n + q]; r[S_W] = T(0.0);
+    r[S_H1] = S[2 * n + q]; r[S_M1] = S[3 * n + q]; r[S_W1] = T(0.0);
+    r[S_H2] = T(0.0); r[S_M2] = T(0.0); r[S_W2] = T(0.0);
+    r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = T(0.0);
   }
   if (rx) { r[S_M] = -r[S_M]; r[S_H1] = -r[S_H1]; r[S_W1] = -r[S_W1]; r[S_M2] = -r[S_M2]; r[S_BX] = -r[S_BX]; }
   if (ry) { r[S_W] = -r[S_W]; r[S_W1] = -r[S_W1]; r[S_H2] = -r[S_H2]; r[S_M2] = -r[S_M2]; r[S_BY] = -r[S_BY]; }
@@ -111,19 +118,22 @@ __device__ __forceinline__ void load_rec(const KArgs& a, const double* __restric
 
 // Node fluxes through LDS: slot k of a NodeF at lane l is sn[k][l].
 constexpr int NNODE = 18;
-__device__ __forceinline__ void nodef_store(double (*sn)[64], int l, const NodeF& X) {
-  const double v[NNODE] = {X.e, X.mn, X.mt, X.d0, X.d1, X.d2, X.f0, X.f1, X.f2,
+template <class T>
+__device__ __forceinline__ void nodef_store(T (*sn)[64], int l, const NodeF<T>& X) {
+  const T v[NNODE] = {X.e, X.mn, X.mt, X.d0, X.d1, X.d2, X.f0, X.f1, X.f2,
                            X.p0, X.p1, X.p2, X.q0, X.q1, X.q2, X.b, X.bn, X.bt};
 #pragma unroll
   for (int k = 0; k < NNODE; ++k) sn[k][l] = v[k];
 }
-__device__ __forceinline__ void nodef_load(double (*sn)[64], int l, NodeF& X) {
+template <class T>
+__device__ __forceinline__ void nodef_load(T (*sn)[64], int l, NodeF<T>& X) {
   X.e = sn[0][l]; X.mn = sn[1][l]; X.mt = sn[2][l]; X.d0 = sn[3][l]; X.d1 = sn[4][l]; X.d2 = sn[5][l];
   X.f0 = sn[6][l]; X.f1 = sn[7][l]; X.f2 = sn[8][l]; X.p0 = sn[9][l]; X.p1 = sn[10][l]; X.p2 = sn[11][l];
   X.q0 = sn[12][l]; X.q1 = sn[13][l]; X.q2 = sn[14][l]; X.b = sn[15][l]; X.bn = sn[16][l]; X.bt = sn[17][l];
 }
 
-__device__ __forceinline__ void ifo_to_array(const IfO& o, double* v) {
+template <class T>
+__device__ __forceinline__ void ifo_to_array(const IfO<T>& o, T* v) {
   v[0] = o.F0; v[1] = o.F1; v[2] = o.F2; v[3] = o.B0; v[4] = o.B1; v[5] = o.B2; v[6] = o.P0;
   v[7] = o.P1; v[8] = o.P2; v[9] = o.PB; v[10] = o.M0; v[11] = o.M1; v[12] = o.M2; v[13] = o.MB;
 }
@@ -131,18 +141,18 @@ __device__ __forceinline__ void ifo_to_array(const IfO& o, double* v) {
 // Add the contribution of one sweep (left/right interfaces l, r, spacing id = 1/dx) to the
 // 9 right-hand-side slots R (2D order eta, m, w, H1, M1, W1, H2, M2, W2). un/ut/dn/dt are the
 // slots of the frame's normal and tangential momentum and derivative triples.
-template <int DIR>
-__device__ __forceinline__ void assemble(const double* l, const double* r, double eta, double H1, double H2,
-                                         double g, double id, double R[9]) {
+template <int DIR, class T>
+__device__ __forceinline__ void assemble(const T* l, const T* r, T eta, T H1, T H2,
+                                         T g, T id, T R[9]) {
   const int un = DIR == 0 ? 1 : 2, ut = DIR == 0 ? 2 : 1;
   const int dn = DIR == 0 ? 3 : 6, dt = DIR == 0 ? 6 : 3;  // first slot of D_n, D_t
-  const double Hn = DIR == 0 ? H1 : H2, Ht = DIR == 0 ? H2 : H1;
-  const double db0 = r[3] - l[3], db1 = r[4] - l[4], db2 = r[5] - l[5];
-  const double ge = g * eta;
+  const T Hn = DIR == 0 ? H1 : H2, Ht = DIR == 0 ? H2 : H1;
+  const T db0 = r[3] - l[3], db1 = r[4] - l[4], db2 = r[5] - l[5];
+  const T ge = g * eta;
   R[0] -= ((r[0] - l[0]) + ge * db0) * id;
   R[un] -= ((r[1] - l[1]) + ge * db1) * id;
   R[ut] -= ((r[2] - l[2]) + ge * db2) * id;
-  const double gn = g * Hn, gt = g * Ht;
+  const T gn = g * Hn, gt = g * Ht;
   R[dn + 0] -= ((r[6] - l[6]) + gn * db0) * id;
   R[dn + un] -= ((r[7] - l[7]) + gn * db1 + ge * (r[9] - l[9])) * id;
   R[dn + ut] -= ((r[8] - l[8]) + gn * db2) * id;
@@ -151,73 +161,76 @@ __device__ __forceinline__ void assemble(const double* l, const double* r, doubl
   R[dt + ut] -= ((r[12] - l[12]) + gt * db2) * id;
 }
 
-__device__ __forceinline__ double wave_max(double v) {
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
   return v;
 }
 
 // Speeds |u| + c, |v| + c of a node for the next Lax-Friedrichs split; flags dry / non-finite.
-__device__ __forceinline__ void speeds(double e, double m, double w, double b, double g, double& ax, double& ay,
+template <class T>
+__device__ __forceinline__ void speeds(T e, T m, T w, T b, T g, T& ax, T& ay,
                                        int& err) {
-  const double h = e - b;
-  if (!(h > 0.0)) { err |= (h == h) ? ERR_DRY : ERR_NONFINITE; return; }
-  const double c = sqrt(g * h), ih = 1.0 / h;
-  const double sx = fabs(m * ih) + c, sy = fabs(w * ih) + c;
-  if (!(sx <= DBL_MAX) || !(sy <= DBL_MAX)) { err |= ERR_NONFINITE; return; }
+  const T h = e - b;
+  if (!(h > T(0.0))) { err |= (h == h) ? ERR_DRY : ERR_NONFINITE; return; }
+  const T c = sqrt(g * h), ih = T(1.0) / h;
+  const T sx = fabs(m * ih) + c, sy = fabs(w * ih) + c;
+  if (!(sx <= big_value<T>()) || !(sy <= big_value<T>())) { err |= ERR_NONFINITE; return; }
   ax = fmax(ax, sx);
   ay = fmax(ay, sy);
 }
 
-__device__ __forceinline__ void flush_speeds(const KArgs& a, double ax, double ay, int err) {
+template <class T>
+__device__ __forceinline__ void flush_speeds(const KArgs<T>& a, T ax, T ay, int err) {
   ax = wave_max(ax);
   ay = wave_max(ay);
   int e = err;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, WAVE);
   if (threadIdx.x == 0) {
-    atomicMax(&a.a_out[0], (unsigned long long)__double_as_longlong(ax));
-    atomicMax(&a.a_out[1], (unsigned long long)__double_as_longlong(ay));
+    atomicMax(&a.a_out[0], (unsigned long long)__double_as_longlong((double)ax));
+    atomicMax(&a.a_out[1], (unsigned long long)__double_as_longlong((double)ay));
     if (e) atomicOr(&a.sc->err, e);
   }
 }
 
 // --------------------------------------------------------------------------- the fused stage
 // One wavefront's tile: output columns [tx*60, tx*60+60) of rows [ty*rows, ty*rows+rows).
-template <int DIM, int MODE>
-__device__ __forceinline__ void stage_tile(const KArgs& a, int tx, int ty) {
+template <class T, int DIM, int MODE>
+__device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
   if (MODE != MODE_RHS && a.sc->active == 0) return;
-  __shared__ double sn[NNODE][WAVE];  // x-frame fluxes of the current row, one node per lane
-  __shared__ double sf[14][WAVE];     // x-interface quantities (lane l: interface left of its column)
-  __shared__ double sy[14][WAVE];     // y-interface quantities of the previous row (own lane)
+  __shared__ T sn[NNODE][WAVE];  // x-frame fluxes of the current row, one node per lane
+  __shared__ T sf[14][WAVE];     // x-interface quantities (lane l: interface left of its column)
+  __shared__ T sy[14][WAVE];     // y-interface quantities of the previous row (own lane)
   const int lane = threadIdx.x;
   const int c = tx * OUT_COLS - 2 + lane;  // this lane's column
   const int r0 = DIM == 2 ? ty * a.rows : 0;
   const int r1 = DIM == 2 ? min(r0 + a.rows, a.ny) : 1;
   const bool col_out = lane >= 2 && lane < WAVE - 2 && c < a.nx;
   const int cq = col_out ? c : 0;  // a column that is always inside the grid
-  const double axl = bits2d(a.a_in[0]), ayl = bits2d(a.a_in[1]);
+  const T axl = T(bits2d(a.a_in[0])), ayl = T(bits2d(a.a_in[1]));
   const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
-  const double dt = MODE == MODE_RHS ? 0.0 : a.sc->dt;
+  const T dt = MODE == MODE_RHS ? T(0.0) : T(a.sc->dt);
   const int nu = DIM == 2 ? 3 : 2, nd = DIM == 2 ? 6 : 2;
   const int la = max(lane - 2, 0), lb = max(lane - 1, 0), ld = min(lane + 1, WAVE - 1);
-  double amx = 0.0, amy = 0.0;
+  T amx = T(0.0), amy = T(0.0);
   int err = 0;
 
   // y window: raw records of rows r-1, r, r+1 (2D); the flux of interface r-1/2 waits in sy
-  double wm1[NREC], w0[NREC], wp1[NREC];
+  T wm1[NREC], w0[NREC], wp1[NREC];
   if (DIM == 2) {
-    double wm2[NREC];
+    T wm2[NREC];
     load_rec<DIM>(a, a.S, c, r0 - 2, wm2);
     load_rec<DIM>(a, a.S, c, r0 - 1, wm1);
     load_rec<DIM>(a, a.S, c, r0, w0);
     load_rec<DIM>(a, a.S, c, r0 + 1, wp1);
-    IfO o;
-    auto fy = [&](int k, NodeF& X) {
+    IfO<T> o;
+    auto fy = [&](int k, NodeF<T>& X) {
       node_frame<1>(k == 0 ? wm2 : (k == 1 ? wm1 : (k == 2 ? w0 : wp1)), a.g, X);
     };
     interface_flux(fy, ayl, a.dy, a.eps, a.g, o);
-    double v[14];
+    T v[14];
     ifo_to_array(o, v);
 #pragma unroll
     for (int k = 0; k < 14; ++k) sy[k][lane] = v[k];
@@ -228,51 +241,51 @@ __device__ __forceinline__ void stage_tile(const KArgs& a, int tx, int ty) {
   for (int r = r0; r < r1; ++r) {
     const size_t q = (size_t)r * a.nx + cq;
     // loads whose latency the x-sweep hides: the next row of the window, U^n and D^{n,mod}
-    double wp2[NREC];
+    T wp2[NREC];
     if (DIM == 2) load_rec<DIM>(a, a.S, c, r + 2, wp2);
-    double un_[3], dn_[6];
+    T un_[3], dn_[6];
     if (MODE == MODE_STAGE1 || MODE == MODE_STAGE2) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) if (k < nu) un_[k] = a.Sn[k * n + q];
 #pragma unroll
       for (int k = 0; k < 6; ++k) if (k < nd) dn_[k] = a.Dn[k * n + q];
     }
-    double R[9];
+    T R[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = 0.0;
-    const double eta = w0[S_ETA], H1 = w0[S_H1], H2 = w0[S_H2];
+    for (int k = 0; k < 9; ++k) R[k] = T(0.0);
+    const T eta = w0[S_ETA], H1 = w0[S_H1], H2 = w0[S_H2];
 
     // x-sweep of row r: each lane's x-frame fluxes are computed once and shared through LDS
     __syncthreads();  // the previous row's readers of sn and sf are done
     {
-      NodeF me;
+      NodeF<T> me;
       node_frame<0>(w0, a.g, me);
       nodef_store(sn, lane, me);
       __syncthreads();
-      IfO o;
-      auto fx = [&](int k, NodeF& X) {
+      IfO<T> o;
+      auto fx = [&](int k, NodeF<T>& X) {
         if (k == 2) X = me;
         else nodef_load(sn, k == 0 ? la : (k == 1 ? lb : ld), X);
       };
       interface_flux(fx, axl, a.dx, a.eps, a.g, o);
-      double xl[14];
+      T xl[14];
       ifo_to_array(o, xl);
 #pragma unroll
       for (int k = 0; k < 14; ++k) sf[k][lane] = xl[k];
       __syncthreads();
-      double xr[14];
+      T xr[14];
 #pragma unroll
       for (int k = 0; k < 14; ++k) xr[k] = sf[k][ld];
       assemble<0>(xl, xr, eta, H1, H2, a.g, a.idx, R);
     }
     // y-sweep: interface r+1/2 from rows r-1 .. r+2
     if (DIM == 2) {
-      IfO o;
-      auto fy = [&](int k, NodeF& X) {
+      IfO<T> o;
+      auto fy = [&](int k, NodeF<T>& X) {
         node_frame<1>(k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2)), a.g, X);
       };
       interface_flux(fy, ayl, a.dy, a.eps, a.g, o);
-      double ynew[14], yprev[14];
+      T ynew[14], yprev[14];
       ifo_to_array(o, ynew);
 #pragma unroll
       for (int k = 0; k < 14; ++k) { yprev[k] = sy[k][lane]; sy[k][lane] = ynew[k]; }
@@ -290,13 +303,13 @@ __device__ __forceinline__ void stage_tile(const KArgs& a, int tx, int ty) {
       } else {
         // limited derivatives of this stage's state at the node (Sec. 2.2); the x-neighbours'
         // surface, momenta and x-derivatives are the first six slots of their shared fluxes
-        double Dm[6];
+        T Dm[6];
         if (a.limiter) {
           limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], sn[0][lb], sn[1][lb], sn[2][lb], sn[0][ld], sn[1][ld],
                       sn[2][ld], sn[3][lb], sn[4][lb], sn[5][lb], sn[3][ld], sn[4][ld], sn[5][ld], a.dx, a.idx,
                       a.eps, a.g, Dm);
           if (DIM == 2) {
-            double o3[3];
+            T o3[3];
             limit_frame(w0[S_ETA], w0[S_W], w0[S_M], w0[S_B], wm1[S_ETA], wm1[S_W], wm1[S_M], wp1[S_ETA],
                         wp1[S_W], wp1[S_M], wm1[S_H2], wm1[S_W2], wm1[S_M2], wp1[S_H2], wp1[S_W2], wp1[S_M2], a.dy,
                         a.idy, a.eps, a.g, o3);
@@ -309,30 +322,30 @@ __device__ __forceinline__ void stage_tile(const KArgs& a, int tx, int ty) {
         // SSP-RK3 combination (eq. (2.11)), written over a common denominator
         const int uslot[3] = {S_ETA, S_M, S_W};
         const int rd[6] = {3, 4, 5, 6, 7, 8};
-        double Unew[3] = {0.0, 0.0, 0.0};
+        T Unew[3] = {T(0.0), T(0.0), T(0.0)};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (k >= nu) break;
-          const double u = w0[uslot[k]] + dt * R[k];
-          double v;
+          const T u = w0[uslot[k]] + dt * R[k];
+          T v;
           if (MODE == MODE_STAGE0) v = u;
-          else if (MODE == MODE_STAGE1) v = (3.0 * un_[k] + u) * 0.25;
-          else v = (un_[k] + 2.0 * u) / 3.0;
+          else if (MODE == MODE_STAGE1) v = (T(3.0) * un_[k] + u) * T(0.25);
+          else v = (un_[k] + T(2.0) * u) / T(3.0);
           Unew[k] = v;
           a.out[k * n + q] = v;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           if (k >= nd) break;
-          const double u = Dm[k] + dt * R[rd[k]];
-          double v;
+          const T u = Dm[k] + dt * R[rd[k]];
+          T v;
           if (MODE == MODE_STAGE0) {
             v = u;
             a.Dn_out[k * n + q] = Dm[k];
           } else if (MODE == MODE_STAGE1) {
-            v = (3.0 * dn_[k] + u) * 0.25;
+            v = (T(3.0) * dn_[k] + u) * T(0.25);
           } else {
-            v = (dn_[k] + 2.0 * u) / 3.0;
+            v = (dn_[k] + T(2.0) * u) / T(3.0);
           }
           a.out[(nu + k) * n + q] = v;
         }
@@ -347,27 +360,27 @@ __device__ __forceinline__ void stage_tile(const KArgs& a, int tx, int ty) {
   if (MODE != MODE_RHS) flush_speeds(a, amx, amy, err);
 }
 
-template <int DIM, int MODE>
-__global__ __launch_bounds__(WAVE) void k_stage(KArgs a) {
-  stage_tile<DIM, MODE>(a, blockIdx.x, blockIdx.y);
+template <class T, int DIM, int MODE>
+__global__ __launch_bounds__(WAVE) void k_stage(KArgs<T> a) {
+  stage_tile<T, DIM, MODE>(a, blockIdx.x, blockIdx.y);
 }
 
 // --------------------------------------------------------------------------- small kernels
 // Lax-Friedrichs speeds of a state (grid-stride), max-reduced into out[2].
-template <int DIM>
-__global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ S, const double* __restrict__ b, size_t n,
-                                               double g, unsigned long long* out, int* errp) {
-  double ax = 0.0, ay = 0.0;
+template <class T, int DIM>
+__global__ __launch_bounds__(256) void k_alpha(const T* __restrict__ S, const T* __restrict__ b, size_t n,
+                                               T g, unsigned long long* out, int* errp) {
+  T ax = T(0.0), ay = T(0.0);
   int err = 0;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
-    speeds(S[q], S[n + q], DIM == 2 ? S[2 * n + q] : 0.0, b[q], g, ax, ay, err);
+    speeds(S[q], S[n + q], DIM == 2 ? S[2 * n + q] : T(0.0), b[q], g, ax, ay, err);
   ax = wave_max(ax);
   ay = wave_max(ay);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, WAVE);
   if ((threadIdx.x & (WAVE - 1)) == 0) {
-    atomicMax(&out[0], (unsigned long long)__double_as_longlong(ax));
-    atomicMax(&out[1], (unsigned long long)__double_as_longlong(ay));
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong((double)ax));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong((double)ay));
     if (err) atomicOr(errp, err);
   }
 }
@@ -413,16 +426,16 @@ __global__ void k_prologue(DevScal* s, int dim, int fixed_dt, double fdt, double
 }
 
 // Stand-alone limiter: one thread per node, neighbours read directly.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_limit(KArgs a) {
+template <class T, int DIM>
+__global__ __launch_bounds__(256) void k_limit(KArgs<T> a) {
   const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(q % a.nx), j = (int)(q / a.nx);
-    double c0[NREC], xm[NREC], xp[NREC];
+    T c0[NREC], xm[NREC], xp[NREC];
     load_rec<DIM>(a, a.S, i, j, c0);
     load_rec<DIM>(a, a.S, i - 1, j, xm);
     load_rec<DIM>(a, a.S, i + 1, j, xp);
-    double D[3];
+    T D[3];
     limit_frame(c0[S_ETA], c0[S_M], c0[S_W], c0[S_B], xm[S_ETA], xm[S_M], xm[S_W], xp[S_ETA], xp[S_M], xp[S_W],
                 xm[S_H1], xm[S_M1], xm[S_W1], xp[S_H1], xp[S_M1], xp[S_W1], a.dx, a.idx, a.eps, a.g, D);
     if (DIM == 1) {
@@ -431,7 +444,7 @@ __global__ __launch_bounds__(256) void k_limit(KArgs a) {
       continue;
     }
     a.out[q] = D[0]; a.out[n + q] = D[1]; a.out[2 * n + q] = D[2];
-    double ym[NREC], yp[NREC];
+    T ym[NREC], yp[NREC];
     load_rec<DIM>(a, a.S, i, j - 1, ym);
     load_rec<DIM>(a, a.S, i, j + 1, yp);
     limit_frame(c0[S_ETA], c0[S_W], c0[S_M], c0[S_B], ym[S_ETA], ym[S_W], ym[S_M], yp[S_ETA], yp[S_W], yp[S_M],
@@ -447,15 +460,17 @@ using namespace swe;
 
 struct swe_hweno_ctx {
   swe_hweno_params p{};
+  int f32 = 0;                // arithmetic and storage type: 0 = double, 1 = float
+  size_t esz = sizeof(double);
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // capture stream for the per-step graphs
   int nf = 0, nd = 0;
   size_t n = 0;
-  double *b = nullptr, *bx = nullptr, *by = nullptr;
-  double *S1 = nullptr, *S2 = nullptr, *Dn = nullptr;
+  void *b = nullptr, *bx = nullptr, *by = nullptr;  // planes of the context's type
+  void *S1 = nullptr, *S2 = nullptr, *Dn = nullptr;
   DevScal* sc = nullptr;
   hipGraphExec_t g1 = nullptr, g8 = nullptr;
-  const double* g_state = nullptr;
+  const void* g_state = nullptr;
   int g_tend = 0;
   int rows = ROWS_DEFAULT;  // rows marched per wave (2D), chosen at init
   // kernel timing: event pairs around stage kernels (slot 0 = bare right-hand side, 1..3 = stages)
@@ -492,18 +507,21 @@ unsigned long long dbits(double v) {
   return u;
 }
 
-KArgs base_args(const swe_hweno_ctx* c) {
-  KArgs a;
+template <class T> bool is_type(const swe_hweno_ctx* c) { return c->f32 == (sizeof(T) == sizeof(float) ? 1 : 0); }
+
+template <class T> KArgs<T> base_args(const swe_hweno_ctx* c) {
+  KArgs<T> a;
   std::memset(&a, 0, sizeof a);
-  a.b = c->b; a.bx = c->bx; a.by = c->by;
+  a.b = (const T*)c->b; a.bx = (const T*)c->bx; a.by = (const T*)c->by;
   a.sc = c->sc;
   a.nx = c->p.nx; a.ny = c->p.dim == 2 ? c->p.ny : 1;
   a.bcx = c->p.bc_x; a.bcy = c->p.bc_y;
   a.limiter = (c->p.flags & SWE_NO_LIMITER) ? 0 : 1;
-  a.dx = (c->p.x1 - c->p.x0) / c->p.nx;
-  a.dy = c->p.dim == 2 ? (c->p.y1 - c->p.y0) / c->p.ny : 1.0;
-  a.idx = 1.0 / a.dx; a.idy = 1.0 / a.dy;
-  a.g = c->p.g; a.eps = c->p.eps;
+  const double dx = (c->p.x1 - c->p.x0) / c->p.nx;
+  const double dy = c->p.dim == 2 ? (c->p.y1 - c->p.y0) / c->p.ny : 1.0;
+  a.dx = T(dx); a.dy = T(dy);
+  a.idx = T(1.0 / dx); a.idy = T(1.0 / dy);
+  a.g = T(c->p.g); a.eps = T(c->p.eps);
   a.rows = c->rows;
   return a;
 }
@@ -514,17 +532,19 @@ dim3 stage_grid(const swe_hweno_ctx* c) {
   return dim3(gx, gy, 1);
 }
 
-template <int MODE> void launch_stage_mode(const swe_hweno_ctx* c, const KArgs& a, hipStream_t s) {
-  if (c->p.dim == 2) hipLaunchKernelGGL((k_stage<2, MODE>), stage_grid(c), dim3(WAVE), 0, s, a);
-  else hipLaunchKernelGGL((k_stage<1, MODE>), stage_grid(c), dim3(WAVE), 0, s, a);
+template <class T, int MODE> void launch_stage_mode(const swe_hweno_ctx* c, const KArgs<T>& a, hipStream_t s) {
+  if (c->p.dim == 2) hipLaunchKernelGGL((k_stage<T, 2, MODE>), stage_grid(c), dim3(WAVE), 0, s, a);
+  else hipLaunchKernelGGL((k_stage<T, 1, MODE>), stage_grid(c), dim3(WAVE), 0, s, a);
 }
 
-void launch_alpha(const swe_hweno_ctx* c, const double* S, unsigned long long* out, hipStream_t s) {
+template <class T> void launch_alpha(const swe_hweno_ctx* c, const T* S, unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, s, out, 0ull, 0ull);
   const size_t blocks = (c->n + 255) / 256;
   const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
-  if (c->p.dim == 2) hipLaunchKernelGGL(k_alpha<2>, dim3(grid), dim3(256), 0, s, S, c->b, c->n, c->p.g, out, &c->sc->err);
-  else hipLaunchKernelGGL(k_alpha<1>, dim3(grid), dim3(256), 0, s, S, c->b, c->n, c->p.g, out, &c->sc->err);
+  if (c->p.dim == 2)
+    hipLaunchKernelGGL((k_alpha<T, 2>), dim3(grid), dim3(256), 0, s, S, (const T*)c->b, c->n, T(c->p.g), out, &c->sc->err);
+  else
+    hipLaunchKernelGGL((k_alpha<T, 1>), dim3(grid), dim3(256), 0, s, S, (const T*)c->b, c->n, T(c->p.g), out, &c->sc->err);
 }
 
 hipEvent_t take_event(swe_hweno_ctx* c) {
@@ -543,13 +563,13 @@ int time_begin(swe_hweno_ctx* c, hipStream_t s) {
   if (!c || !c->timing || s != c->stream) return -1;
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return -1;
-  hipEventRecord(a, s);
+  (void)hipEventRecord(a, s);
   c->pending.push_back({a, b, -1});
   return (int)c->pending.size() - 1;
 }
 void time_end(swe_hweno_ctx* c, int id, int slot, hipStream_t s) {
   if (id < 0) return;
-  hipEventRecord(c->pending[id].b, s);
+  (void)hipEventRecord(c->pending[id].b, s);
   c->pending[id].slot = slot;
 }
 
@@ -569,28 +589,33 @@ void collect_timing(swe_hweno_ctx* c) {
 
 // One step on stream s: prologue and three fused stages; U^n is `state`, updated in place.
 // With timing on (direct launches only) every stage kernel is bracketed by an event pair.
-void enqueue_step(swe_hweno_ctx* c, double* state, int use_tend, hipStream_t s) {
-  const KArgs base = base_args(c);
+template <class T> void enqueue_step(swe_hweno_ctx* c, T* state, int use_tend, hipStream_t s) {
+  const KArgs<T> base = base_args<T>(c);
   const bool fa = (c->p.flags & SWE_FIXED_ALPHA) != 0;
+  const double dx = (c->p.x1 - c->p.x0) / c->p.nx;
+  const double dy = c->p.dim == 2 ? (c->p.y1 - c->p.y0) / c->p.ny : 1.0;
   hipLaunchKernelGGL(k_prologue, dim3(1), dim3(64), 0, s, c->sc, c->p.dim, (c->p.flags & SWE_FIXED_DT) ? 1 : 0,
-                     c->p.fixed_dt, c->p.cfl, base.dx, base.dy, use_tend);
-  KArgs a = base;
-  a.S = state; a.out = c->S1; a.Dn_out = c->Dn;
+                     c->p.fixed_dt, c->p.cfl, dx, dy, use_tend);
+  T* S1 = (T*)c->S1;
+  T* S2 = (T*)c->S2;
+  T* Dn = (T*)c->Dn;
+  KArgs<T> a = base;
+  a.S = state; a.out = S1; a.Dn_out = Dn;
   a.a_in = fa ? c->sc->a_fix : c->sc->a_n; a.a_out = c->sc->a_1;
   int id = time_begin(c, s);
-  launch_stage_mode<MODE_STAGE0>(c, a, s);
+  launch_stage_mode<T, MODE_STAGE0>(c, a, s);
   time_end(c, id, 1, s);
   a = base;
-  a.S = c->S1; a.Sn = state; a.Dn = c->Dn; a.out = c->S2;
+  a.S = S1; a.Sn = state; a.Dn = Dn; a.out = S2;
   a.a_in = fa ? c->sc->a_fix : c->sc->a_1; a.a_out = c->sc->a_2;
   id = time_begin(c, s);
-  launch_stage_mode<MODE_STAGE1>(c, a, s);
+  launch_stage_mode<T, MODE_STAGE1>(c, a, s);
   time_end(c, id, 2, s);
   a = base;
-  a.S = c->S2; a.Sn = state; a.Dn = c->Dn; a.out = state;
+  a.S = S2; a.Sn = state; a.Dn = Dn; a.out = state;
   a.a_in = fa ? c->sc->a_fix : c->sc->a_2; a.a_out = c->sc->a_next;
   id = time_begin(c, s);
-  launch_stage_mode<MODE_STAGE2>(c, a, s);
+  launch_stage_mode<T, MODE_STAGE2>(c, a, s);
   time_end(c, id, 3, s);
 }
 
@@ -636,14 +661,171 @@ void destroy_graphs(swe_hweno_ctx* c) {
   c->g_state = nullptr;
 }
 
-int capture(swe_hweno_ctx* c, double* state, int steps, int use_tend, hipGraphExec_t* out) {
+template <class T> int capture(swe_hweno_ctx* c, T* state, int steps, int use_tend, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return SWE_EHIP;
-  for (int k = 0; k < steps; ++k) enqueue_step(c, state, use_tend, c->cap);
+  for (int k = 0; k < steps; ++k) enqueue_step<T>(c, state, use_tend, c->cap);
   if (hipStreamEndCapture(c->cap, &g) != hipSuccess || !g) return SWE_EHIP;
   const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   return hip_status(e);
+}
+
+// ------------------------------------------------------------------ typed bodies of the entry points
+template <class T>
+int init_impl(const swe_hweno_params* p, const T* b, const T* bx, const T* by, void* stream, swe_hweno_ctx** out) {
+  if (!out) return SWE_EINVAL;
+  *out = nullptr;
+  if (!params_ok(p) || !b || !bx || (p->dim == 2 && !by)) return SWE_EINVAL;
+  swe_hweno_ctx* c = new (std::nothrow) swe_hweno_ctx();
+  if (!c) return SWE_ENOMEM;
+  c->p = *p;
+  c->f32 = sizeof(T) == sizeof(float) ? 1 : 0;
+  c->esz = sizeof(T);
+  c->stream = (hipStream_t)stream;
+  c->nf = p->dim == 2 ? 9 : 4;
+  c->nd = p->dim == 2 ? 6 : 2;
+  c->n = (size_t)p->nx * (size_t)(p->dim == 2 ? p->ny : 1);
+  const size_t plane = c->n * sizeof(T);
+  bool ok = hipMalloc(&c->b, plane * 3) == hipSuccess;
+  ok = ok && hipMalloc(&c->S1, plane * c->nf) == hipSuccess;
+  ok = ok && hipMalloc(&c->S2, plane * c->nf) == hipSuccess;
+  ok = ok && hipMalloc(&c->Dn, plane * c->nd) == hipSuccess;
+  ok = ok && hipMalloc(&c->sc, sizeof(DevScal)) == hipSuccess;
+  if (!ok) { swe_hweno_destroy(c); return SWE_ENOMEM; }
+  c->bx = (T*)c->b + c->n;
+  c->by = (T*)c->b + 2 * c->n;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || cus <= 0)
+      cus = 256;
+    c->rows = choose_rows(p->nx, p->dim == 2 ? p->ny : 1, 4 * cus);
+  }
+  ok = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipMemcpyAsync(c->b, b, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(c->bx, bx, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  if (p->dim == 2) ok = ok && hipMemcpyAsync(c->by, by, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  else ok = ok && hipMemsetAsync(c->by, 0, plane, c->stream) == hipSuccess;
+  DevScal init;
+  std::memset(&init, 0, sizeof init);
+  init.a_fix[0] = dbits(p->alpha_x);
+  init.a_fix[1] = dbits(p->dim == 2 ? p->alpha_y : 0.0);
+  ok = ok && hipMemcpyAsync(c->sc, &init, sizeof init, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) { swe_hweno_destroy(c); return SWE_EHIP; }
+  *out = c;
+  return SWE_OK;
+}
+
+template <class T> int rhs_impl(swe_hweno_ctx* c, const T* state, T* rhs, double alpha_x, double alpha_y) {
+  if (!c || !state || !rhs || state == rhs || !is_type<T>(c)) return SWE_EINVAL;
+  if (alpha_x >= 0 && (!(alpha_x > 0) || !std::isfinite(alpha_x))) return SWE_EINVAL;
+  if (alpha_x > 0 && c->p.dim == 2 && (!(alpha_y > 0) || !std::isfinite(alpha_y))) return SWE_EINVAL;
+  const size_t bytes = c->n * c->nf * sizeof(T);
+  if ((const char*)rhs < (const char*)state + bytes && (const char*)state < (const char*)rhs + bytes) return SWE_EINVAL;
+  if (alpha_x < 0) launch_alpha<T>(c, state, c->sc->a_rhs, c->stream);
+  else
+    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, c->sc->a_rhs, dbits(alpha_x),
+                       dbits(c->p.dim == 2 ? alpha_y : 0.0));
+  KArgs<T> a = base_args<T>(c);
+  a.S = state; a.out = rhs; a.a_in = c->sc->a_rhs;
+  const int id = time_begin(c, c->stream);
+  launch_stage_mode<T, MODE_RHS>(c, a, c->stream);
+  time_end(c, id, 0, c->stream);
+  return hip_status(hipGetLastError());
+}
+
+template <class T> int limit_impl(swe_hweno_ctx* c, const T* state, T* dmod) {
+  if (!c || !state || !dmod || !is_type<T>(c)) return SWE_EINVAL;
+  KArgs<T> a = base_args<T>(c);
+  a.S = state; a.out = dmod;
+  const size_t blocks = (c->n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 8192 ? blocks : 8192);
+  if (c->p.dim == 2) hipLaunchKernelGGL((k_limit<T, 2>), dim3(grid), dim3(256), 0, c->stream, a);
+  else hipLaunchKernelGGL((k_limit<T, 1>), dim3(grid), dim3(256), 0, c->stream, a);
+  return hip_status(hipGetLastError());
+}
+
+template <class T> int alpha_impl(swe_hweno_ctx* c, const T* state, double* alpha_host) {
+  if (!c || !state || !alpha_host || !is_type<T>(c)) return SWE_EINVAL;
+  launch_alpha<T>(c, state, c->sc->a_rhs, c->stream);
+  unsigned long long u[2];
+  if (hipMemcpyAsync(u, c->sc->a_rhs, sizeof u, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
+  const int e = take_device_error(c);
+  std::memcpy(&alpha_host[0], &u[0], 8);
+  std::memcpy(&alpha_host[1], &u[1], 8);
+  return e;
+}
+
+template <class T> int step_impl(swe_hweno_ctx* c, T* state, double dt, double* dt_used) {
+  if (!c || !state || !is_type<T>(c)) return SWE_EINVAL;
+  if (!(dt <= DBL_MAX)) return SWE_EINVAL;
+  const swe_hweno_params saved = c->p;
+  if (dt > 0) { c->p.flags |= SWE_FIXED_DT; c->p.fixed_dt = dt; }
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c->stream, c->sc, 0.0);
+  launch_alpha<T>(c, state, c->sc->a_next, c->stream);
+  enqueue_step<T>(c, state, 0, c->stream);
+  c->p = saved;
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  if (dt_used) {
+    if (hipMemcpyAsync(dt_used, &c->sc->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return SWE_EHIP;
+    return take_device_error(c);
+  }
+  return SWE_OK;
+}
+
+template <class T> int run_impl(swe_hweno_ctx* c, T* state, int nsteps, double t_end, double* t_out, int* steps_out) {
+  if (!c || !state || !is_type<T>(c)) return SWE_EINVAL;
+  if (!(t_end <= DBL_MAX) || (nsteps <= 0 && !(t_end > 0))) return SWE_EINVAL;
+  const int use_tend = t_end > 0 ? 1 : 0;
+  if (!c->timing && (c->g_state != state || c->g_tend != use_tend)) {
+    destroy_graphs(c);
+    int e = capture<T>(c, state, 1, use_tend, &c->g1);
+    if (!e) e = capture<T>(c, state, 8, use_tend, &c->g8);
+    if (e) { destroy_graphs(c); return e; }
+    c->g_state = state;
+    c->g_tend = use_tend;
+  }
+  // t = 0, t_end, steps = 0 and alpha of the initial state
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c->stream, c->sc, t_end);
+  launch_alpha<T>(c, state, c->sc->a_next, c->stream);
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  int done = 0;
+  const int chunk = 64;
+  for (;;) {
+    int todo = nsteps > 0 ? nsteps - done : chunk;
+    if (todo <= 0) break;
+    if (use_tend && todo > chunk) todo = chunk;
+    int k = 0;
+    if (c->timing) {
+      for (; k < todo; ++k) enqueue_step<T>(c, state, use_tend, c->stream);
+      if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+    }
+    for (; k + 8 <= todo; k += 8)
+      if (hipGraphLaunch(c->g8, c->stream) != hipSuccess) return SWE_EHIP;
+    for (; k < todo; ++k)
+      if (hipGraphLaunch(c->g1, c->stream) != hipSuccess) return SWE_EHIP;
+    done += todo;
+    if (use_tend) {
+      int active = 0;
+      if (hipMemcpyAsync(&active, &c->sc->active, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return SWE_EHIP;
+      if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
+      if (!active) break;
+    }
+  }
+  double t = 0;
+  int steps = 0;
+  if (hipMemcpyAsync(&t, &c->sc->t, sizeof t, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
+  if (hipMemcpyAsync(&steps, &c->sc->steps, sizeof steps, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return SWE_EHIP;
+  const int e = take_device_error(c);
+  if (c->timing) collect_timing(c);
+  if (t_out) *t_out = t;
+  if (steps_out) *steps_out = steps;
+  return e;
 }
 
 }  // namespace
@@ -680,173 +862,57 @@ const char* swe_hweno_strerror(int code) {
 
 int swe_hweno_init(const swe_hweno_params* p, const double* b, const double* bx, const double* by, void* stream,
                    swe_hweno_ctx** out) {
-  if (!out) return SWE_EINVAL;
-  *out = nullptr;
-  if (!params_ok(p) || !b || !bx || (p->dim == 2 && !by)) return SWE_EINVAL;
-  swe_hweno_ctx* c = new (std::nothrow) swe_hweno_ctx();
-  if (!c) return SWE_ENOMEM;
-  c->p = *p;
-  c->stream = (hipStream_t)stream;
-  c->nf = p->dim == 2 ? 9 : 4;
-  c->nd = p->dim == 2 ? 6 : 2;
-  c->n = (size_t)p->nx * (size_t)(p->dim == 2 ? p->ny : 1);
-  const size_t plane = c->n * sizeof(double);
-  bool ok = hipMalloc(&c->b, plane * 3) == hipSuccess;
-  ok = ok && hipMalloc(&c->S1, plane * c->nf) == hipSuccess;
-  ok = ok && hipMalloc(&c->S2, plane * c->nf) == hipSuccess;
-  ok = ok && hipMalloc(&c->Dn, plane * c->nd) == hipSuccess;
-  ok = ok && hipMalloc(&c->sc, sizeof(DevScal)) == hipSuccess;
-  if (!ok) { swe_hweno_destroy(c); return SWE_ENOMEM; }
-  c->bx = c->b + c->n;
-  c->by = c->b + 2 * c->n;
-  {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-        hipSuccess || cus <= 0)
-      cus = 256;
-    c->rows = choose_rows(p->nx, p->dim == 2 ? p->ny : 1, 4 * cus);
-  }
-  ok = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipMemcpyAsync(c->b, b, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
-  ok = ok && hipMemcpyAsync(c->bx, bx, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
-  if (p->dim == 2) ok = ok && hipMemcpyAsync(c->by, by, plane, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
-  else ok = ok && hipMemsetAsync(c->by, 0, plane, c->stream) == hipSuccess;
-  DevScal init;
-  std::memset(&init, 0, sizeof init);
-  init.a_fix[0] = dbits(p->alpha_x);
-  init.a_fix[1] = dbits(p->dim == 2 ? p->alpha_y : 0.0);
-  ok = ok && hipMemcpyAsync(c->sc, &init, sizeof init, hipMemcpyHostToDevice, c->stream) == hipSuccess;
-  ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
-  if (!ok) { swe_hweno_destroy(c); return SWE_EHIP; }
-  *out = c;
-  return SWE_OK;
+  return init_impl<double>(p, b, bx, by, stream, out);
+}
+int swe_hweno_init_f32(const swe_hweno_params* p, const float* b, const float* bx, const float* by, void* stream,
+                       swe_hweno_ctx** out) {
+  return init_impl<float>(p, b, bx, by, stream, out);
 }
 
 void swe_hweno_destroy(swe_hweno_ctx* c) {
   if (!c) return;
-  if (c->stream || c->b) hipStreamSynchronize(c->stream);
+  if (c->stream || c->b) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   collect_timing(c);
-  for (hipEvent_t e : c->pool) hipEventDestroy(e);
-  if (c->cap) hipStreamDestroy(c->cap);
-  if (c->b) hipFree(c->b);
-  if (c->S1) hipFree(c->S1);
-  if (c->S2) hipFree(c->S2);
-  if (c->Dn) hipFree(c->Dn);
-  if (c->sc) hipFree(c->sc);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->b) (void)hipFree(c->b);
+  if (c->S1) (void)hipFree(c->S1);
+  if (c->S2) (void)hipFree(c->S2);
+  if (c->Dn) (void)hipFree(c->Dn);
+  if (c->sc) (void)hipFree(c->sc);
   delete c;
 }
 
 int swe_hweno_rhs(swe_hweno_ctx* c, const double* state, double* rhs, double alpha_x, double alpha_y) {
-  if (!c || !state || !rhs || state == rhs) return SWE_EINVAL;
-  if (alpha_x >= 0 && (!(alpha_x > 0) || !std::isfinite(alpha_x))) return SWE_EINVAL;
-  if (alpha_x > 0 && c->p.dim == 2 && (!(alpha_y > 0) || !std::isfinite(alpha_y))) return SWE_EINVAL;
-  const size_t bytes = c->n * c->nf * sizeof(double);
-  if ((const char*)rhs < (const char*)state + bytes && (const char*)state < (const char*)rhs + bytes) return SWE_EINVAL;
-  if (alpha_x < 0) launch_alpha(c, state, c->sc->a_rhs, c->stream);
-  else
-    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, c->stream, c->sc->a_rhs, dbits(alpha_x),
-                       dbits(c->p.dim == 2 ? alpha_y : 0.0));
-  KArgs a = base_args(c);
-  a.S = state; a.out = rhs; a.a_in = c->sc->a_rhs;
-  const int id = time_begin(c, c->stream);
-  launch_stage_mode<MODE_RHS>(c, a, c->stream);
-  time_end(c, id, 0, c->stream);
-  return hip_status(hipGetLastError());
+  return rhs_impl<double>(c, state, rhs, alpha_x, alpha_y);
+}
+int swe_hweno_rhs_f32(swe_hweno_ctx* c, const float* state, float* rhs, double alpha_x, double alpha_y) {
+  return rhs_impl<float>(c, state, rhs, alpha_x, alpha_y);
 }
 
-int swe_hweno_limit(swe_hweno_ctx* c, const double* state, double* dmod) {
-  if (!c || !state || !dmod) return SWE_EINVAL;
-  KArgs a = base_args(c);
-  a.S = state; a.out = dmod;
-  const size_t blocks = (c->n + 255) / 256;
-  const unsigned grid = (unsigned)(blocks < 8192 ? blocks : 8192);
-  if (c->p.dim == 2) hipLaunchKernelGGL(k_limit<2>, dim3(grid), dim3(256), 0, c->stream, a);
-  else hipLaunchKernelGGL(k_limit<1>, dim3(grid), dim3(256), 0, c->stream, a);
-  return hip_status(hipGetLastError());
-}
+int swe_hweno_limit(swe_hweno_ctx* c, const double* state, double* dmod) { return limit_impl<double>(c, state, dmod); }
+int swe_hweno_limit_f32(swe_hweno_ctx* c, const float* state, float* dmod) { return limit_impl<float>(c, state, dmod); }
 
 int swe_hweno_alpha(swe_hweno_ctx* c, const double* state, double* alpha_host) {
-  if (!c || !state || !alpha_host) return SWE_EINVAL;
-  launch_alpha(c, state, c->sc->a_rhs, c->stream);
-  unsigned long long u[2];
-  if (hipMemcpyAsync(u, c->sc->a_rhs, sizeof u, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
-  const int e = take_device_error(c);
-  std::memcpy(&alpha_host[0], &u[0], 8);
-  std::memcpy(&alpha_host[1], &u[1], 8);
-  return e;
+  return alpha_impl<double>(c, state, alpha_host);
+}
+int swe_hweno_alpha_f32(swe_hweno_ctx* c, const float* state, double* alpha_host) {
+  return alpha_impl<float>(c, state, alpha_host);
 }
 
 int swe_hweno_step(swe_hweno_ctx* c, double* state, double dt, double* dt_used) {
-  if (!c || !state) return SWE_EINVAL;
-  if (!(dt <= DBL_MAX)) return SWE_EINVAL;
-  const swe_hweno_params saved = c->p;
-  if (dt > 0) { c->p.flags |= SWE_FIXED_DT; c->p.fixed_dt = dt; }
-  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c->stream, c->sc, 0.0);
-  launch_alpha(c, state, c->sc->a_next, c->stream);
-  enqueue_step(c, state, 0, c->stream);
-  c->p = saved;
-  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
-  if (dt_used) {
-    if (hipMemcpyAsync(dt_used, &c->sc->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-      return SWE_EHIP;
-    return take_device_error(c);
-  }
-  return SWE_OK;
+  return step_impl<double>(c, state, dt, dt_used);
+}
+int swe_hweno_step_f32(swe_hweno_ctx* c, float* state, double dt, double* dt_used) {
+  return step_impl<float>(c, state, dt, dt_used);
 }
 
 int swe_hweno_run(swe_hweno_ctx* c, double* state, int nsteps, double t_end, double* t_out, int* steps_out) {
-  if (!c || !state) return SWE_EINVAL;
-  if (!(t_end <= DBL_MAX) || (nsteps <= 0 && !(t_end > 0))) return SWE_EINVAL;
-  const int use_tend = t_end > 0 ? 1 : 0;
-  if (!c->timing && (c->g_state != state || c->g_tend != use_tend)) {
-    destroy_graphs(c);
-    int e = capture(c, state, 1, use_tend, &c->g1);
-    if (!e) e = capture(c, state, 8, use_tend, &c->g8);
-    if (e) { destroy_graphs(c); return e; }
-    c->g_state = state;
-    c->g_tend = use_tend;
-  }
-  // t = 0, t_end, steps = 0 and alpha of the initial state
-  {
-    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c->stream, c->sc, t_end);
-    launch_alpha(c, state, c->sc->a_next, c->stream);
-  }
-  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
-  int done = 0;
-  const int chunk = 64;
-  for (;;) {
-    int todo = nsteps > 0 ? nsteps - done : chunk;
-    if (todo <= 0) break;
-    if (use_tend && todo > chunk) todo = chunk;
-    int k = 0;
-    if (c->timing) {
-      for (; k < todo; ++k) enqueue_step(c, state, use_tend, c->stream);
-      if (hipGetLastError() != hipSuccess) return SWE_EHIP;
-    }
-    for (; k + 8 <= todo; k += 8)
-      if (hipGraphLaunch(c->g8, c->stream) != hipSuccess) return SWE_EHIP;
-    for (; k < todo; ++k)
-      if (hipGraphLaunch(c->g1, c->stream) != hipSuccess) return SWE_EHIP;
-    done += todo;
-    if (use_tend) {
-      int active = 0;
-      if (hipMemcpyAsync(&active, &c->sc->active, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-        return SWE_EHIP;
-      if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
-      if (!active) break;
-    }
-  }
-  double t = 0;
-  int steps = 0;
-  if (hipMemcpyAsync(&t, &c->sc->t, sizeof t, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return SWE_EHIP;
-  if (hipMemcpyAsync(&steps, &c->sc->steps, sizeof steps, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-    return SWE_EHIP;
-  const int e = take_device_error(c);
-  if (c->timing) collect_timing(c);
-  if (t_out) *t_out = t;
-  if (steps_out) *steps_out = steps;
-  return e;
+  return run_impl<double>(c, state, nsteps, t_end, t_out, steps_out);
+}
+int swe_hweno_run_f32(swe_hweno_ctx* c, float* state, int nsteps, double t_end, double* t_out, int* steps_out) {
+  return run_impl<float>(c, state, nsteps, t_end, t_out, steps_out);
 }
 
 int swe_hweno_set_timing(swe_hweno_ctx* c, int on) {

@@ -1,7 +1,8 @@
 """Thin Python front end of the HIP solver: torch tensors in, the C ABI underneath.
 
-PyTorch provides device memory and streams only. A state is a contiguous float64 CUDA tensor
-of shape (4, nx) in 1D (eta, m, H, M) or (9, ny, nx) in 2D (eta, m, w, H1, M1, W1, H2, M2, W2).
+PyTorch provides device memory and streams only. A state is a contiguous CUDA tensor of shape
+(4, nx) in 1D (eta, m, H, M) or (9, ny, nx) in 2D (eta, m, w, H1, M1, W1, H2, M2, W2), float64,
+or float32 for a single-precision solver (dtype=torch.float32, the library's _f32 entry points).
 """
 from __future__ import annotations
 
@@ -13,9 +14,9 @@ from . import _lib
 from ._lib import BC_PERIODIC, BC_REFLECTIVE, FIXED_ALPHA, FIXED_DT, NO_LIMITER, SweError  # noqa: F401
 
 
-def _dev(t: torch.Tensor, name: str) -> int:
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
-        raise TypeError(f"{name} must be a float64 CUDA tensor")
+def _dev(t: torch.Tensor, name: str, dtype=torch.float64) -> int:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dtype:
+        raise TypeError(f"{name} must be a {dtype} CUDA tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
@@ -25,8 +26,13 @@ class Solver:
     """One solver context (swe_hweno_init ... swe_hweno_destroy) on the current CUDA stream."""
 
     def __init__(self, dim, nx, ny, domain, b, bx, by=None, bc=(BC_PERIODIC, BC_PERIODIC), g=9.812, cfl=0.6,
-                 eps=1e-6, flags=0, fixed_dt=0.0, alpha=(0.0, 0.0), stream=None):
+                 eps=1e-6, flags=0, fixed_dt=0.0, alpha=(0.0, 0.0), stream=None, dtype=torch.float64):
         L = _lib.lib()
+        if dtype not in (torch.float64, torch.float32):
+            raise TypeError("dtype must be torch.float64 or torch.float32")
+        self.dtype = dtype
+        sfx = "_f32" if dtype == torch.float32 else ""
+        self._fn = {k: getattr(L, f"swe_hweno_{k}{sfx}") for k in ("init", "rhs", "limit", "alpha", "step", "run")}
         self.dim, self.nx, self.ny = dim, nx, (ny if dim == 2 else 1)
         self.nf = 9 if dim == 2 else 4
         self.shape = (9, self.ny, nx) if dim == 2 else (4, nx)
@@ -39,27 +45,27 @@ class Solver:
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         keep = [b, bx] + ([by] if dim == 2 else [])
-        ptrs = [_dev(t, n) for t, n in zip(keep, ("b", "bx", "by"))]
+        ptrs = [_dev(t, n, dtype) for t, n in zip(keep, ("b", "bx", "by"))]
         for t in keep:
             if t.numel() != nx * self.ny:
                 raise ValueError("bottom planes must have nx*ny elements")
         ctx = ctypes.c_void_p()
-        _lib.check(L.swe_hweno_init(ctypes.byref(p), ptrs[0], ptrs[1], ptrs[2] if dim == 2 else None,
+        _lib.check(self._fn["init"](ctypes.byref(p), ptrs[0], ptrs[1], ptrs[2] if dim == 2 else None,
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)), "swe_hweno_init")
         self._ctx = ctx
         self._L = L
 
     @classmethod
-    def from_problem(cls, prob, device="cuda", **kw):
+    def from_problem(cls, prob, device="cuda", dtype=torch.float64, **kw):
         """Build from a paper_2208_01260_amd.inputs.Problem (bottom copied to the device)."""
-        t = lambda a: torch.from_numpy(a).to(device=device, dtype=torch.float64).contiguous()
+        t = lambda a: torch.from_numpy(a).to(device=device, dtype=dtype).contiguous()
         d = dict(bc=prob.bc, g=prob.g, cfl=prob.cfl, eps=prob.eps)
         d.update(kw)
         return cls(prob.dim, prob.nx, prob.ny, prob.domain, t(prob.b), t(prob.bx),
-                   t(prob.by) if prob.dim == 2 else None, **d)
+                   t(prob.by) if prob.dim == 2 else None, dtype=dtype, **d)
 
     def _state(self, s, name="state"):
-        ptr = _dev(s, name)
+        ptr = _dev(s, name, self.dtype)
         if tuple(s.shape) != self.shape:
             raise ValueError(f"{name} must have shape {self.shape}")
         return ptr
@@ -67,32 +73,31 @@ class Solver:
     def rhs(self, state, out=None, alpha=None):
         out = torch.empty_like(state) if out is None else out
         ax, ay = (-1.0, -1.0) if alpha is None else (float(alpha[0]), float(alpha[1]))
-        _lib.check(self._L.swe_hweno_rhs(self._ctx, self._state(state), self._state(out, "out"), ax, ay),
-                   "swe_hweno_rhs")
+        _lib.check(self._fn["rhs"](self._ctx, self._state(state), self._state(out, "out"), ax, ay), "swe_hweno_rhs")
         return out
 
     def limit(self, state, out=None):
         nd = 6 if self.dim == 2 else 2
         shape = (nd,) + self.shape[1:]
-        out = torch.empty(shape, dtype=torch.float64, device=state.device) if out is None else out
-        _lib.check(self._L.swe_hweno_limit(self._ctx, self._state(state), _dev(out, "out")), "swe_hweno_limit")
+        out = torch.empty(shape, dtype=self.dtype, device=state.device) if out is None else out
+        _lib.check(self._fn["limit"](self._ctx, self._state(state), _dev(out, "out", self.dtype)), "swe_hweno_limit")
         return out
 
     def alpha(self, state):
         a = (ctypes.c_double * 2)()
-        _lib.check(self._L.swe_hweno_alpha(self._ctx, self._state(state), a), "swe_hweno_alpha")
+        _lib.check(self._fn["alpha"](self._ctx, self._state(state), a), "swe_hweno_alpha")
         return a[0], a[1]
 
     def step(self, state, dt=0.0, sync=False):
         used = ctypes.c_double()
-        _lib.check(self._L.swe_hweno_step(self._ctx, self._state(state), float(dt),
-                                          ctypes.byref(used) if sync else None), "swe_hweno_step")
+        _lib.check(self._fn["step"](self._ctx, self._state(state), float(dt), ctypes.byref(used) if sync else None),
+                   "swe_hweno_step")
         return used.value if sync else None
 
     def run(self, state, nsteps=0, t_end=0.0):
         t, k = ctypes.c_double(), ctypes.c_int()
-        _lib.check(self._L.swe_hweno_run(self._ctx, self._state(state), int(nsteps), float(t_end), ctypes.byref(t),
-                                         ctypes.byref(k)), "swe_hweno_run")
+        _lib.check(self._fn["run"](self._ctx, self._state(state), int(nsteps), float(t_end), ctypes.byref(t),
+                                   ctypes.byref(k)), "swe_hweno_run")
         return t.value, k.value
 
     def set_timing(self, on=True):

@@ -67,6 +67,9 @@ def test_init_rejects_bad_params_before_any_device_call(L, bad):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     assert L.swe_hweno_init(ctypes.byref(p), fake, fake, fake, None, ctypes.byref(ctx)) == -1
     assert ctx.value is None
+    ctx = ctypes.c_void_p(123)
+    assert L.swe_hweno_init_f32(ctypes.byref(p), fake, fake, fake, None, ctypes.byref(ctx)) == -1
+    assert ctx.value is None
 
 
 def test_null_arguments_rejected(L):
@@ -92,6 +95,12 @@ def test_null_arguments_rejected(L):
     assert L.swe_hweno_batch_autotune(None, None) == -1
     assert L.swe_hweno_batch_sync(None) == -1
     L.swe_hweno_batch_destroy(None)
+    assert L.swe_hweno_init_f32(ctypes.byref(p), None, None, None, None, ctypes.byref(ctx)) == -1
+    assert L.swe_hweno_rhs_f32(None, None, None, -1.0, -1.0) == -1
+    assert L.swe_hweno_limit_f32(None, None, None) == -1
+    assert L.swe_hweno_step_f32(None, None, 0.0, None) == -1
+    assert L.swe_hweno_run_f32(None, None, 1, 0.0, None, None) == -1
+    assert L.swe_hweno_alpha_f32(None, None, None) == -1
 
 
 def test_batch_init_rejects_bad_arguments(L):
