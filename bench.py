@@ -115,6 +115,44 @@ def single_precision(args, torch, pr, f_rhs):
             "ms_per_step": step_ms, "cell_rhs_per_s": 3.0 * cells / (step_ms * 1e-3)}
 
 
+def adjoint_cost(args, torch):
+    """Reverse mode on the adjoint workload: 256^2, 100 steps at a fixed dt with frozen speeds,
+    checkpoint every 10 steps. Cost = swe_hweno_run_vjp (checkpointed forward, recomputation and
+    reverse) over the plain forward run of the same steps."""
+    from paper_2208_01260_amd import inputs
+    from paper_2208_01260_amd.solver import FIXED_ALPHA, FIXED_DT, Solver
+
+    pr = inputs.c5_adjoint(256)
+    nsteps, ck = 100, 10
+    st0 = torch.from_numpy(pr.state).to("cuda:0").contiguous()
+    with Solver.from_problem(pr) as s:
+        ax, ay = s.alpha(st0)
+    al = (1.1 * ax, 1.1 * ay)
+    dt = 0.6 / (al[0] / pr.dx + al[1] / pr.dy)
+    with Solver.from_problem(pr, flags=FIXED_DT | FIXED_ALPHA, fixed_dt=dt, alpha=al) as s:
+        st = st0.clone()
+        s.run(st, nsteps=nsteps)
+        sbar = torch.randn_like(st0)
+        s.run_vjp(st0, nsteps, sbar, ck)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.copy_(st0)
+            s.run(st, nsteps=nsteps)
+        torch.cuda.synchronize()
+        fwd = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.run_vjp(st0, nsteps, sbar, ck)
+        torch.cuda.synchronize()
+        bwd = (time.perf_counter() - t0) / reps
+    print(f"[bench] adjoint: forward {fwd * 1e3:.2f} ms, reverse {bwd * 1e3:.2f} ms ({bwd / fwd:.2f}x)",
+          file=sys.stderr, flush=True)
+    return {"workload": "256x256, 100 steps, fixed dt, frozen alpha, checkpoint every 10", "forward_ms": fwd * 1e3,
+            "reverse_ms": bwd * 1e3, "reverse_over_forward": bwd / fwd}
+
+
 def batched(args, torch):
     """Batched forward solver: `count` independent instances of uneven sizes (64..512 nodes per
     side, seeded bottoms and Gaussian humps, reflective walls), every stage one launch over all
@@ -166,6 +204,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle sample: steps of the same workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-fp32", action="store_true", help="skip the single-precision leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode leg")
     ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-loop", type=int, default=64, help="instances timed one by one for comparison")
@@ -281,6 +320,8 @@ def main():
         line["fp32"] = single_precision(args, torch, pr, f_rhs)
     if args.batch_count > 0:
         line["batched"] = batched(args, torch)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_cost(args, torch)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_steps)

@@ -201,6 +201,45 @@ int swe_hweno_batch_sync(swe_hweno_batch* bt);
 /* Free the batch (synchronises first). NULL is a no-op. */
 void swe_hweno_batch_destroy(swe_hweno_batch* bt);
 
+/* ------------------------------------------------------------------------------------------
+ * Adjoint (reverse mode), 2D FP64 contexts. Vector-Jacobian products of the scheme with the
+ * Lax-Friedrichs speeds frozen: of the right-hand side (eq. (3.8), with the split of eq. (2.4),
+ * the weights of eqs. (2.5)-(2.7), the source split of Step 2 and the mixed terms of eq. (3.7)),
+ * of the limiter (Sec. 2.2, eq. (2.13)) and of a run of SSP-RK3 steps (eq. (2.11)) at a fixed dt.
+ * The bottom b and its slopes bx, by enter as independent inputs; swe_hweno_bottom_slopes and
+ * its transpose tie them together when the gradient with respect to b alone is wanted. Work
+ * buffers (about 230 planes at a checkpoint interval of 10, plus the checkpoints) are allocated
+ * on first use and kept with the context. All arrays are DEVICE arrays; outputs are overwritten.
+ * ------------------------------------------------------------------------------------------ */
+
+/* rbar (state layout) is the adjoint of R(state) with alpha = (alpha_x, alpha_y) > 0 fixed.
+ * sbar (state layout) receives rbar^T dR/dstate; bbar, bxbar, bybar (planes) receive
+ * rbar^T dR/db, dR/dbx, dR/dby. */
+int swe_hweno_rhs_vjp(swe_hweno_ctx* ctx, const double* state, double alpha_x, double alpha_y, const double* rbar,
+                      double* sbar, double* bbar, double* bxbar, double* bybar);
+
+/* dmbar (6 planes: H1, M1, W1, H2, M2, W2) is the adjoint of Lim(state); sbar (state layout)
+ * and bbar receive its products with dLim/dstate and dLim/db. */
+int swe_hweno_limit_vjp(swe_hweno_ctx* ctx, const double* state, const double* dmbar, double* sbar, double* bbar);
+
+/* Reverse of nsteps steps of swe_hweno_run from state0 (not modified). The context must have
+ * SWE_FIXED_DT and SWE_FIXED_ALPHA set (the map is then smooth). sbar_T (state layout) is the
+ * adjoint of the final state; sbar_0 receives the adjoint of state0 and bbar, bxbar, bybar
+ * those of the bottom planes. The stage states are recomputed from checkpoints stored every
+ * checkpoint_every steps (>= 1). Synchronises; returns SWE_EDRY / SWE_ENONFINITE if the
+ * recomputed forward run met them. */
+int swe_hweno_run_vjp(swe_hweno_ctx* ctx, const double* state0, int nsteps, int checkpoint_every,
+                      const double* sbar_T, double* sbar_0, double* bbar, double* bxbar, double* bybar);
+
+/* Bottom slopes by the fourth-order centred difference
+ *   bx_i = (b_{i-2} - 8 b_{i-1} + 8 b_{i+1} - b_{i+2}) / (12 dx)   (by likewise along y),
+ * with b extended through the boundary (periodic wrap, or even about a reflective wall), for
+ * the grid of params (dim 2), on a hipStream_t. The _vjp form adds the transpose of that map
+ * applied to (bxbar, bybar) into bbar. */
+int swe_hweno_bottom_slopes(const swe_hweno_params* params, const double* b, double* bx, double* by, void* stream);
+int swe_hweno_bottom_slopes_vjp(const swe_hweno_params* params, const double* bxbar, const double* bybar,
+                                double* bbar, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,8 @@ def lib():
             "orc_count_rhs": (I, [P, _D, _D, _D, _D, Dd, Dd, ctypes.POINTER(ctypes.c_longlong)]),
             "orc_count_limit": (I, [P, _D, _D, _D, _D, ctypes.POINTER(ctypes.c_longlong)]),
             "orc_rhs_jvp": (I, [P, _D, _D, _D, _D, _D, _D, _D, _D, Dd, Dd, _D, _D]),
+            "orc_limit_jvp": (I, [P, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]),
+            "orc_run_jvp": (I, [P, _D, _D, _D, _D, _D, _D, _D, _D, I, _D, _D]),
             "orc_hw_candidates": (None, [_D, _D, Dd, _D]),
             "orc_hw_beta": (None, [_D, _D, Dd, _D]),
             "orc_hw_weights": (None, [_D, Dd, _D]),
@@ -250,6 +252,33 @@ def rhs_jvp(p, state, dstate, b, bx, by, db, dbx, dby, alpha_x, alpha_y):
     out, dout = np.empty_like(state), np.empty_like(state)
     _check(lib().orc_rhs_jvp(ctypes.byref(p), _p(state), _p(dstate), _p(b), _p(bx), _p(by), _p(db), _p(dbx),
                              _p(dby), alpha_x, alpha_y, _p(out), _p(dout)))
+    return out, dout
+
+
+def limit_jvp(p, state, dstate, b, bx, by, db, dbx, dby):
+    """Forward-mode tangent of the limiter: returns (dmod, ddmod)."""
+    state, dstate = _f64(state), _f64(dstate)
+    b, bx, by = _bottom(p, b, bx, by)
+    db, dbx = _f64(db), _f64(dbx)
+    dby = _f64(dby) if p.dim == 2 else None
+    nd = 2 if p.dim == 1 else 6
+    out = np.empty((nd,) + state.shape[1:], dtype=np.float64)
+    dout = np.empty_like(out)
+    _check(lib().orc_limit_jvp(ctypes.byref(p), _p(state), _p(dstate), _p(b), _p(bx), _p(by), _p(db), _p(dbx),
+                               _p(dby), _p(out), _p(dout)))
+    return out, dout
+
+
+def run_jvp(p, state, dstate, b, bx, by, db, dbx, dby, nsteps):
+    """Forward-mode tangent of nsteps steps (use FIXED_DT | FIXED_ALPHA for a smooth map):
+    returns (final state, its directional derivative)."""
+    state, dstate = _f64(state), _f64(dstate)
+    b, bx, by = _bottom(p, b, bx, by)
+    db, dbx = _f64(db), _f64(dbx)
+    dby = _f64(dby) if p.dim == 2 else None
+    out, dout = np.empty_like(state), np.empty_like(state)
+    _check(lib().orc_run_jvp(ctypes.byref(p), _p(state), _p(dstate), _p(b), _p(bx), _p(by), _p(db), _p(dbx),
+                             _p(dby), int(nsteps), _p(out), _p(dout)))
     return out, dout
 
 

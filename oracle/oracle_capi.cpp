@@ -206,6 +206,53 @@ int orc_run_delta_f128(const orc_params* p, const double* state, const double* b
   return run_delta<__float128>(p, state, b, bx, by, nsteps, t_end, delta, t_out, steps_out);
 }
 
+// Forward-mode tangents (Dual<double>) of the limiter and of a run: the value and the
+// directional derivative along (dstate, db, dbx, dby). A run is differentiable when alpha and
+// dt are fixed (flags FIXED_ALPHA | FIXED_DT); otherwise the max in alpha is differentiated
+// along its active branch.
+int orc_limit_jvp(const orc_params* p, const double* state, const double* dstate, const double* b, const double* bx,
+                  const double* by, const double* db, const double* dbx, const double* dby, double* dmod,
+                  double* ddmod) {
+  if (!valid(p) || !state || !dstate || !b || !bx || !db || !dbx) return E_INVAL;
+  if (p->dim == 2 && (!by || !dby)) return E_INVAL;
+  using D = Dual<double>;
+  const size_t n = nodes(p), N = (size_t)nfields(p) * n;
+  std::vector<D> bb(n), bbx(n), bby(n), S(N);
+  for (size_t q = 0; q < n; ++q) {
+    bb[q] = D(b[q], db[q]); bbx[q] = D(bx[q], dbx[q]);
+    bby[q] = p->dim == 2 ? D(by[q], dby[q]) : D(0.0, 0.0);
+  }
+  for (size_t q = 0; q < N; ++q) S[q] = D(state[q], dstate[q]);
+  Scheme<D> s;
+  s.setup(convert<D>(p), bb.data(), bbx.data(), bby.data());
+  const size_t ND = (size_t)s.nd * n;
+  std::vector<D> M(ND);
+  s.limit(S.data(), S.data() + (size_t)s.nu * n, M.data());
+  for (size_t q = 0; q < ND; ++q) { dmod[q] = M[q].v; ddmod[q] = M[q].d; }
+  return OK;
+}
+
+int orc_run_jvp(const orc_params* p, const double* state, const double* dstate, const double* b, const double* bx,
+                const double* by, const double* db, const double* dbx, const double* dby, int nsteps,
+                double* out, double* dout) {
+  if (!valid(p) || !state || !dstate || !b || !bx || !db || !dbx || nsteps < 1) return E_INVAL;
+  if (p->dim == 2 && (!by || !dby)) return E_INVAL;
+  using D = Dual<double>;
+  const size_t n = nodes(p), N = (size_t)nfields(p) * n;
+  std::vector<D> bb(n), bbx(n), bby(n), S(N);
+  for (size_t q = 0; q < n; ++q) {
+    bb[q] = D(b[q], db[q]); bbx[q] = D(bx[q], dbx[q]);
+    bby[q] = p->dim == 2 ? D(by[q], dby[q]) : D(0.0, 0.0);
+  }
+  for (size_t q = 0; q < N; ++q) S[q] = D(state[q], dstate[q]);
+  Scheme<D> s;
+  s.setup(convert<D>(p), bb.data(), bbx.data(), bby.data());
+  int k = 0;
+  const int e = s.run(S.data(), nsteps, 0.0, nullptr, &k);
+  for (size_t q = 0; q < N; ++q) { out[q] = S[q].v; dout[q] = S[q].d; }
+  return e;
+}
+
 // Count the arithmetic of one right-hand side (alpha given): counts = {add/sub, mul, div, sqrt, cmp}.
 int orc_count_rhs(const orc_params* p, const double* state, const double* b, const double* bx, const double* by,
                   double alpha_x, double alpha_y, long long* counts) {

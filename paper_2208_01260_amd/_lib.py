@@ -25,7 +25,9 @@ EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alph
            "swe_hweno_batch_init", "swe_hweno_batch_run", "swe_hweno_batch_set_rows", "swe_hweno_batch_autotune",
            "swe_hweno_batch_sync", "swe_hweno_batch_destroy",
            "swe_hweno_init_f32", "swe_hweno_rhs_f32", "swe_hweno_limit_f32", "swe_hweno_alpha_f32",
-           "swe_hweno_step_f32", "swe_hweno_run_f32")
+           "swe_hweno_step_f32", "swe_hweno_run_f32",
+           "swe_hweno_rhs_vjp", "swe_hweno_limit_vjp", "swe_hweno_run_vjp", "swe_hweno_bottom_slopes",
+           "swe_hweno_bottom_slopes_vjp")
 
 
 class SweError(RuntimeError):
@@ -78,6 +80,11 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_alpha_f32": (I, [vp, dp, ctypes.POINTER(D)]),
         "swe_hweno_step_f32": (I, [vp, dp, D, ctypes.POINTER(D)]),
         "swe_hweno_run_f32": (I, [vp, dp, I, D, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "swe_hweno_rhs_vjp": (I, [vp, dp, D, D, dp, dp, dp, dp, dp]),
+        "swe_hweno_limit_vjp": (I, [vp, dp, dp, dp, dp]),
+        "swe_hweno_run_vjp": (I, [vp, dp, I, I, dp, dp, dp, dp, dp]),
+        "swe_hweno_bottom_slopes": (I, [P, dp, dp, dp, vp]),
+        "swe_hweno_bottom_slopes_vjp": (I, [P, dp, dp, dp, vp]),
         "swe_hweno_sync": (I, [vp]),
         "swe_hweno_destroy": (None, [vp]),
         "swe_hweno_strerror": (ctypes.c_char_p, [I]),

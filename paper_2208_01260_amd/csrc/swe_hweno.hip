@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "hweno_adjoint.hpp"
 #include "hweno_device.hpp"
 #include "swe_hweno.h"
 
@@ -480,7 +481,10 @@ struct swe_hweno_ctx {
   std::vector<hipEvent_t> pool;
   double ms[4] = {0, 0, 0, 0};
   long long launches[4] = {0, 0, 0, 0};
+  void* adj = nullptr;  // work buffers of the adjoint, allocated on first use
 };
+
+void swe_adj_release(swe_hweno_ctx* c);
 
 namespace {
 
@@ -881,6 +885,7 @@ void swe_hweno_destroy(swe_hweno_ctx* c) {
   if (c->S2) (void)hipFree(c->S2);
   if (c->Dn) (void)hipFree(c->Dn);
   if (c->sc) (void)hipFree(c->sc);
+  swe_adj_release(c);
   delete c;
 }
 
@@ -940,3 +945,4 @@ int swe_hweno_sync(swe_hweno_ctx* c) {
 }  // extern "C"
 
 #include "swe_hweno_batch.inc"
+#include "swe_hweno_adjoint.inc"

@@ -119,6 +119,37 @@ class Solver:
     def sync(self):
         _lib.check(self._L.swe_hweno_sync(self._ctx), "swe_hweno_sync")
 
+    # ------------------------------------------------------------------ reverse mode (2D FP64)
+    def _planes(self, like=None):
+        return torch.empty((self.ny, self.nx), dtype=torch.float64, device="cuda") if like is None else like
+
+    def rhs_vjp(self, state, rbar, alpha):
+        """(sbar, bbar, bxbar, bybar) = rbar^T d R(state) / d(state, b, bx, by), alpha frozen."""
+        sbar = torch.empty_like(state)
+        bb, bxb, byb = self._planes(), self._planes(), self._planes()
+        _lib.check(self._L.swe_hweno_rhs_vjp(self._ctx, self._state(state), float(alpha[0]), float(alpha[1]),
+                                             self._state(rbar, "rbar"), sbar.data_ptr(), bb.data_ptr(),
+                                             bxb.data_ptr(), byb.data_ptr()), "swe_hweno_rhs_vjp")
+        return sbar, bb, bxb, byb
+
+    def limit_vjp(self, state, dmbar):
+        """(sbar, bbar) = dmbar^T d Lim(state) / d(state, b)."""
+        sbar = torch.empty_like(state)
+        bb = self._planes()
+        _lib.check(self._L.swe_hweno_limit_vjp(self._ctx, self._state(state), _dev(dmbar, "dmbar"), sbar.data_ptr(),
+                                               bb.data_ptr()), "swe_hweno_limit_vjp")
+        return sbar, bb
+
+    def run_vjp(self, state0, nsteps, sbar_T, checkpoint_every=10):
+        """Reverse of `nsteps` fixed-dt, frozen-alpha steps from state0: returns
+        (sbar_0, bbar, bxbar, bybar) for the adjoint sbar_T of the final state."""
+        sbar0 = torch.empty_like(state0)
+        bb, bxb, byb = self._planes(), self._planes(), self._planes()
+        _lib.check(self._L.swe_hweno_run_vjp(self._ctx, self._state(state0), int(nsteps), int(checkpoint_every),
+                                             self._state(sbar_T, "sbar_T"), sbar0.data_ptr(), bb.data_ptr(),
+                                             bxb.data_ptr(), byb.data_ptr()), "swe_hweno_run_vjp")
+        return sbar0, bb, bxb, byb
+
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self._L.swe_hweno_destroy(self._ctx)

@@ -1,0 +1,325 @@
+"""GPU: the hand-written reverse mode (swe_hweno_rhs_vjp / _limit_vjp / _run_vjp) through the C ABI.
+
+Each vector-Jacobian product is checked against the oracle's forward-mode tangent (Dual numbers
+through the oracle's own scheme) by the transpose identity <rbar, J d> = <J^T rbar, d>, for
+random rbar and random directions d in the state and in each bottom plane separately. Then:
+the well-balance invariant (at a lake at rest the right-hand side vanishes for every bottom, so
+its bottom adjoints vanish to round-off), a multi-segment checkpointed run against the oracle's
+run tangent, and the 256^2 x 100-step gauge-misfit gradient against central differences.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda().contiguous()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def directions(pr, rng):
+    """Random directions scaled per field: state fields by their magnitude, bottom planes by theirs."""
+    def scale(a):
+        m = np.abs(a).max()
+        return m if m > 0 else 1.0
+    ds = np.stack([rng.standard_normal(pr.state.shape[1:]) * scale(pr.state[f]) for f in range(9)])
+    db = rng.standard_normal(pr.b.shape) * scale(pr.b)
+    dbx = rng.standard_normal(pr.b.shape) * scale(pr.bx)
+    dby = rng.standard_normal(pr.b.shape) * scale(pr.by)
+    return ds, db, dbx, dby
+
+
+def cases(I):
+    return [
+        ("c5_48_refl", I.c5_adjoint(48)),
+        ("acc2d_40_periodic", I.paper_accuracy_2d(40)),
+        ("c3_45x38_dam", I.c3_2d(45, ny=38)),
+        ("c2s_37x29", I.c2_2d(37, "smooth", ny=29)),
+    ]
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(a), abs(b), 1e-300)
+
+
+ENVELOPE_FACTOR = 32.0
+
+
+def dot_envelope(jvp, state, seeds=(1, 2)):
+    """Round-off envelope of a dot product <rbar, J(state) d> computed by the oracle: its change
+    when the state moves by about one unit in the last place (random, relative). Near a lake at
+    rest the bottom derivatives of the right-hand side cancel almost exactly, and two FP64 codes
+    that round differently then agree only to this envelope."""
+    base = jvp(state)
+    env = 0.0
+    for sd in seeds:
+        r = np.random.default_rng(sd)
+        env = max(env, abs(jvp(state * (1.0 + 2.0 ** -52 * r.uniform(-1, 1, state.shape))) - base))
+    return base, env
+
+
+def check_dot(what, lhs_fn, state, rhs):
+    lhs, env = dot_envelope(lhs_fn, state)
+    allowed = max(1e-10 * max(abs(lhs), abs(rhs)), ENVELOPE_FACTOR * env)
+    note(f"[adj] {what}: <rbar, J d> = {lhs:.6e}, <J^T rbar, d> = {rhs:.6e}, |diff| {abs(lhs - rhs):.2e}, "
+         f"allowed {allowed:.2e} (envelope {env:.2e})")
+    assert abs(lhs - rhs) <= allowed, (what, lhs, rhs, allowed)
+
+
+def test_rhs_vjp_transpose_identity(oracle_mod, inputs_mod, torch_cuda):
+    from paper_2208_01260_amd.solver import Solver
+
+    O, torch = oracle_mod, torch_cuda
+    rng = np.random.default_rng(11)
+    for name, pr in cases(inputs_mod):
+        p = O.params_of(pr)
+        ax, ay = O.alpha(p, pr.state, pr.b, pr.bx, pr.by)
+        al = (1.05 * ax, 1.05 * ay)
+        rbar = rng.standard_normal(pr.state.shape)
+        with Solver.from_problem(pr) as s:
+            sb, bb, bxb, byb = [host(t) for t in s.rhs_vjp(dev(torch, pr.state), dev(torch, rbar), al)]
+        ds, db, dbx, dby = directions(pr, rng)
+        z = np.zeros_like(pr.b)
+        zs = np.zeros_like(pr.state)
+        for part, d in (("state", (ds, z, z, z)), ("b", (zs, db, z, z)), ("bx", (zs, z, dbx, z)),
+                        ("by", (zs, z, z, dby))):
+            def lhs_fn(st, d=d):
+                _, dR = O.rhs_jvp(p, st, d[0], pr.b, pr.bx, pr.by, d[1], d[2], d[3], al[0], al[1])
+                return float(np.sum(rbar * dR))
+            rhs = float(np.sum(sb * d[0]) + np.sum(bb * d[1]) + np.sum(bxb * d[2]) + np.sum(byb * d[3]))
+            check_dot(f"rhs {name} d{part}", lhs_fn, pr.state, rhs)
+
+
+def test_limit_vjp_transpose_identity(oracle_mod, inputs_mod, torch_cuda):
+    from paper_2208_01260_amd.solver import Solver
+
+    O, torch = oracle_mod, torch_cuda
+    rng = np.random.default_rng(12)
+    for name, pr in cases(inputs_mod):
+        p = O.params_of(pr)
+        dmbar = rng.standard_normal((6,) + pr.b.shape)
+        with Solver.from_problem(pr) as s:
+            sb, bb = [host(t) for t in s.limit_vjp(dev(torch, pr.state), dev(torch, dmbar))]
+        ds, db, _, _ = directions(pr, rng)
+        z = np.zeros_like(pr.b)
+        zs = np.zeros_like(pr.state)
+        for part, d in (("state", (ds, z)), ("b", (zs, db))):
+            def lhs_fn(st, d=d):
+                _, dD = O.limit_jvp(p, st, d[0], pr.b, pr.bx, pr.by, d[1], z, z)
+                return float(np.sum(dmbar * dD))
+            rhs = float(np.sum(sb * d[0]) + np.sum(bb * d[1]))
+            check_dot(f"limiter {name} d{part}", lhs_fn, pr.state, rhs)
+
+
+def test_rhs_vjp_bottom_adjoints_vanish_at_rest(inputs_mod, torch_cuda):
+    """R(lake at rest; b, bx, by) = 0 for every bottom, so its bottom derivatives vanish."""
+    from paper_2208_01260_amd.solver import Solver
+
+    torch = torch_cuda
+    rng = np.random.default_rng(13)
+    for pr in (inputs_mod.c2_2d(48, "rest", ny=40), inputs_mod.paper_lake_2d(40)):
+        rbar = rng.standard_normal(pr.state.shape)
+        with Solver.from_problem(pr) as s:
+            sb, bb, bxb, byb = [host(t) for t in s.rhs_vjp(dev(torch, pr.state), dev(torch, rbar), (3.5, 3.5))]
+        scale = np.abs(sb[0]).max()
+        worst = max(np.abs(bb).max(), np.abs(bxb).max() * pr.dx, np.abs(byb).max() * pr.dy) / scale
+        note(f"[adj] rest {pr.name}: bottom adjoints / state adjoint scale = {worst:.2e}")
+        assert worst <= 1e-11, (pr.name, worst)
+
+
+def fixed_problem(O, pr, nsteps_hint=1, limiter=True):
+    p0 = O.params_of(pr)
+    ax, ay = O.alpha(p0, pr.state, pr.b, pr.bx, pr.by)
+    al = (1.1 * ax, 1.1 * ay)
+    dt = 0.5 / (al[0] / pr.dx + al[1] / pr.dy)
+    flags = O.FIXED_DT | O.FIXED_ALPHA | (0 if limiter else O.NO_LIMITER)
+    p = O.params_of(pr, flags=flags, fixed_dt=dt, alpha_x=(al[0],) * 3, alpha_y=(al[1],) * 3)
+    return p, al, dt, flags
+
+
+@pytest.mark.parametrize("limiter", [True, False])
+def test_run_vjp_against_oracle_tangent(oracle_mod, inputs_mod, torch_cuda, limiter):
+    from paper_2208_01260_amd.solver import Solver
+
+    O, torch = oracle_mod, torch_cuda
+    rng = np.random.default_rng(14)
+    for name, pr in (("c5_40_refl", inputs_mod.c5_adjoint(40)), ("acc2d_32_periodic", inputs_mod.paper_accuracy_2d(32))):
+        nsteps = 12
+        p, al, dt, flags = fixed_problem(O, pr, limiter=limiter)
+        sT_bar = rng.standard_normal(pr.state.shape)
+        res = []
+        with Solver.from_problem(pr, flags=flags, fixed_dt=dt, alpha=al) as s:
+            for ck in (5, 1, 12, 100):
+                res.append([host(t) for t in s.run_vjp(dev(torch, pr.state), nsteps, dev(torch, sT_bar), ck)])
+            # the forward run of the context matches the oracle's fixed-dt run
+            st = dev(torch, pr.state)
+            s.run(st, nsteps=nsteps)
+            ref, _, _ = O.run(p, pr.state, pr.b, pr.bx, pr.by, nsteps=nsteps)
+            assert np.abs(host(st) - ref).max() <= 1e-11 * np.abs(ref).max()
+        for r in res[1:]:  # the checkpoint interval changes nothing
+            for x, y in zip(res[0], r):
+                assert np.array_equal(x, y)
+        sb0, bb, bxb, byb = res[0]
+        ds, db, dbx, dby = directions(pr, rng)
+        _, dT = O.run_jvp(p, pr.state, ds, pr.b, pr.bx, pr.by, db, dbx, dby, nsteps)
+        lhs = float(np.sum(sT_bar * dT))
+        rhs = float(np.sum(sb0 * ds) + np.sum(bb * db) + np.sum(bxb * dbx) + np.sum(byb * dby))
+        note(f"[adj] run {name} limiter={limiter}: <sbar_T, dS_T> = {lhs:.8e}, adjoint {rhs:.8e}, rel {rel(lhs, rhs):.2e}")
+        assert rel(lhs, rhs) <= 1e-10, (name, lhs, rhs)
+
+
+def slopes_np(b, dx, dy, bc):
+    """The fourth-order centred slopes with the boundary extension, written with numpy."""
+    def ext(a, axis, kind):
+        if kind == 0:
+            return np.concatenate([np.take(a, [-2, -1], axis), a, np.take(a, [0, 1], axis)], axis)
+        return np.concatenate([np.flip(np.take(a, [0, 1], axis), axis), a, np.flip(np.take(a, [-2, -1], axis), axis)],
+                              axis)
+    ex = ext(b, 1, bc[0])
+    bx = (ex[:, 0:-4] - 8 * ex[:, 1:-3] + 8 * ex[:, 3:-1] - ex[:, 4:]) / (12 * dx)
+    ey = ext(b, 0, bc[1])
+    by = (ey[0:-4] - 8 * ey[1:-3] + 8 * ey[3:-1] - ey[4:]) / (12 * dy)
+    return bx, by
+
+
+def test_bottom_slopes_and_transpose(inputs_mod, torch_cuda):
+    from paper_2208_01260_amd import adjoint
+
+    torch = torch_cuda
+    rng = np.random.default_rng(15)
+    for pr in (inputs_mod.c5_adjoint(40), inputs_mod.paper_accuracy_2d(24)):
+        b = rng.standard_normal(pr.b.shape)
+        bx, by = adjoint.bottom_slopes(dev(torch, b), pr.domain, pr.bc)
+        rx, ry = slopes_np(b, pr.dx, pr.dy, pr.bc)
+        assert np.abs(host(bx) - rx).max() <= 1e-12 * np.abs(rx).max()
+        assert np.abs(host(by) - ry).max() <= 1e-12 * np.abs(ry).max()
+        u, v, d = rng.standard_normal(b.shape), rng.standard_normal(b.shape), rng.standard_normal(b.shape)
+        bb = torch.zeros_like(dev(torch, b))
+        adjoint.bottom_slopes_vjp(dev(torch, u), dev(torch, v), bb, pr.domain, pr.bc)
+        dx_, dy_ = slopes_np(d, pr.dx, pr.dy, pr.bc)
+        lhs, rhs = float(np.sum(u * dx_) + np.sum(v * dy_)), float(np.sum(host(bb) * d))
+        assert rel(lhs, rhs) <= 1e-12, (lhs, rhs)
+
+
+def test_c5_gauge_gradient(oracle_mod, inputs_mod, torch_cuda):
+    """256^2, 100 steps, checkpoint every 10: gradient of the gauge misfit with respect to b and
+    U0 against the oracle's tangent and central differences."""
+    from paper_2208_01260_amd import adjoint
+
+    O, torch = oracle_mod, torch_cuda
+    pr = inputs_mod.c5_adjoint(256)
+    g = pr.extra["gauges"]
+    nsteps = 100
+    p0 = O.params_of(pr)
+    ax, ay = O.alpha(p0, pr.state, pr.b, pr.bx, pr.by)
+    al = (1.1 * ax, 1.1 * ay)
+    dt = 0.6 / (al[0] / pr.dx + al[1] / pr.dy)
+    b = dev(torch, pr.b)
+    # bottom slopes from the stencil; the state's initial slopes use them too
+    kw = dict(domain=pr.domain, bc=pr.bc, nsteps=nsteps, dt=dt, alpha=al, checkpoint_every=10)
+    # target: the same run over the perturbed bottom
+    with torch.no_grad():
+        tgt = adjoint.run(dev(torch, pr.state), b + dev(torch, pr.extra["target_db"]), **kw)
+    gj = torch.from_numpy(g[:, 0].astype(np.int64)).cuda()
+    gi = torch.from_numpy(g[:, 1].astype(np.int64)).cuda()
+    htgt = (tgt[0] - (b + dev(torch, pr.extra["target_db"])))[gj, gi]
+
+    def loss(state0, bb):
+        sT = adjoint.run(state0, bb, **kw)
+        h = (sT[0] - bb)[gj, gi]
+        return ((h - htgt) ** 2).sum()
+
+    s0 = dev(torch, pr.state).requires_grad_(True)
+    bq = b.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = loss(s0, bq)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    note(f"[adj] C5 loss {L.item():.6e}; forward {1e3 * (t1 - t0):.1f} ms, backward {1e3 * (t2 - t1):.1f} ms")
+    gs, gb = host(s0.grad), host(bq.grad)
+    assert np.isfinite(gs).all() and np.isfinite(gb).all() and np.abs(gb).max() > 0
+    with torch.no_grad():
+        sT_gpu = adjoint.run(dev(torch, pr.state), b, **kw)
+        misfit = host((sT_gpu[0] - b)[gj, gi] - htgt)  # the adjoint's seed is 2 * misfit at the gauges
+
+    # oracle tangent along two smooth random directions (state and bottom together)
+    rng = np.random.default_rng(16)
+    X, Y = inputs_mod.nodes_2d(pr.nx, pr.ny, pr.domain)
+    dx, dy = pr.dx, pr.dy
+    bx0, by0 = slopes_np(pr.b, dx, dy, pr.bc)
+    p = O.params_of(pr, flags=O.FIXED_DT | O.FIXED_ALPHA, fixed_dt=dt, alpha_x=(al[0],) * 3, alpha_y=(al[1],) * 3)
+
+    def smooth_dir():
+        f = np.zeros_like(X)
+        for _ in range(4):
+            cx, cy, w = rng.uniform(0.3, 1.7), rng.uniform(0.3, 1.7), rng.uniform(0.08, 0.2)
+            f += rng.standard_normal() * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * w * w))
+        return f
+
+    for k in range(2):
+        d_b = 1e-2 * smooth_dir()
+        d_s = np.zeros_like(pr.state)
+        d_s[0] = 1e-3 * smooth_dir()
+        d_bx, d_by = slopes_np(d_b, dx, dy, pr.bc)
+        sT, dT = O.run_jvp(p, pr.state, d_s, pr.b, bx0, by0, d_b, d_bx, d_by, nsteps)
+        h = sT[0][g[:, 0], g[:, 1]] - pr.b[g[:, 0], g[:, 1]]
+        dh = dT[0][g[:, 0], g[:, 1]] - d_b[g[:, 0], g[:, 1]]
+        dL_oracle = float(np.sum(2.0 * misfit * dh))
+        dL_adj = float(np.sum(gs * d_s) + np.sum(gb * d_b))
+        note(f"[adj] C5 direction {k}: oracle tangent {dL_oracle:.12e}, adjoint {dL_adj:.12e}, "
+             f"rel {rel(dL_oracle, dL_adj):.2e}; final-state gauge h GPU vs oracle "
+             f"{np.abs(h - host((sT_gpu[0] - b)[gj, gi])).max():.2e}")
+        assert rel(dL_oracle, dL_adj) <= 1e-10, (k, dL_oracle, dL_adj)
+
+    # central differences on 20 random unit directions in b and U0: second order at eps = 1e-6,
+    # (L(+e) - L(-e)) / 2e, and fourth order at eps = 1e-4,
+    # (8 (L(+e) - L(-e)) - (L(+2e) - L(-2e))) / 12e. The loss is ~1e-10 (gauge misfits ~1e-6 on
+    # depths ~1), so at eps = 1e-6 its rounding alone limits the difference quotient to a few 1e-6.
+    worst2 = worst4 = 0.0
+    with torch.no_grad():
+        for k in range(20):
+            d_b = smooth_dir() if k % 2 == 0 else 0.0 * X
+            d_s = np.zeros_like(pr.state)
+            if k % 2 == 1:
+                d_s[0] = smooth_dir()
+            nrm = np.sqrt(np.sum(d_b ** 2) + np.sum(d_s ** 2))
+            d_b, d_s = d_b / nrm, d_s / nrm
+
+            def L_at(c):
+                return loss(dev(torch, pr.state + c * d_s), b + c * dev(torch, d_b)).item()
+
+            e = 1e-6
+            fd2 = (L_at(e) - L_at(-e)) / (2 * e)
+            e = 1e-4
+            fd4 = (8.0 * (L_at(e) - L_at(-e)) - (L_at(2 * e) - L_at(-2 * e))) / (12 * e)
+            ad = float(np.sum(gs * d_s) + np.sum(gb * d_b))
+            worst2 = max(worst2, rel(fd2, ad))
+            worst4 = max(worst4, rel(fd4, ad))
+    note(f"[adj] C5 central differences, 20 directions: worst relative difference {worst2:.2e} (second order, "
+         f"eps 1e-6), {worst4:.2e} (fourth order, eps 1e-4)")
+    assert worst2 <= 1e-5 and worst4 <= 1e-6, (worst2, worst4)
