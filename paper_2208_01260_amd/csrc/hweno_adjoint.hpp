@@ -73,12 +73,35 @@ __device__ __forceinline__ void hweno_side_vjp(double f0, double f1, double f2, 
   s2b += a2b + c2b - K16 * q2b;
 }
 
-// The weights of hweno_side (forward only), for the bottom reconstruction's reverse.
-__device__ __forceinline__ void hweno_weights(double f0, double f1, double f2, double s0, double s1, double s2,
-                                              double eps, double w[3]) {
-  W3<double> ww;
-  (void)hweno_side(f0, f1, f2, s0, s1, s2, eps, ww);
-  w[0] = ww.w1; w[1] = ww.w2; w[2] = ww.w3;
+// Forward HWENO value of one side with its normalised weights w (the formulas of Sec. 2.1 as
+// the reverse below differentiates them).
+__device__ __forceinline__ double side_value(double f0, double f1, double f2, double s0, double s1, double s2,
+                                             double eps, double w[3]) {
+  const double d01 = f0 - f1, d12 = f1 - f2;
+  const double a1 = 3.0 * d01 + s0 + 2.0 * s1, c1 = 2.0 * d01 + s0 + s1;
+  const double a2 = 3.0 * d12 + s2 + 2.0 * s1, c2 = 2.0 * d12 + s2 + s1;
+  const double a3 = (f0 + f2) - 2.0 * f1, c3 = (f0 - f2) + 2.0 * s1;
+  const double t = s1 * s1;
+  const double g1 = t + K133 * (a1 * a1) + K78120 * (c1 * c1) + eps;
+  const double g2 = t + K133 * (a2 * a2) + K78120 * (c2 * c2) + eps;
+  const double g3 = t + K1312 * (a3 * a3) + K78180 * (c3 * c3) + eps;
+  const double e1 = g1 * g1, e2 = g2 * g2, e3 = g3 * g3;
+  const double u1 = 0.3 * (e2 * e3), u2 = 0.3 * (e1 * e3), u3 = 0.4 * (e1 * e2);
+  const double is = rcp((u1 + u2) + u3);
+  w[0] = u1 * is; w[1] = u2 * is; w[2] = u3 * is;
+  const double q1 = 0.5 * (f0 + f1) + K16 * (s0 + 5.0 * s1);
+  const double q2 = 0.5 * (f1 + f2) + K16 * (s1 - s2);
+  const double q3 = K112 * ((f0 + f2) + 10.0 * f1) + 0.5 * s1;
+  return w[0] * q1 + w[1] * q2 + w[2] * q3;
+}
+
+// Candidates combined with given normalised weights (the source split of Step 2).
+__device__ __forceinline__ double with_value(double f0, double f1, double f2, double s0, double s1, double s2,
+                                             const double w[3]) {
+  const double q1 = 0.5 * (f0 + f1) + K16 * (s0 + 5.0 * s1);
+  const double q2 = 0.5 * (f1 + f2) + K16 * (s1 - s2);
+  const double q3 = K112 * ((f0 + f2) + 10.0 * f1) + 0.5 * s1;
+  return w[0] * q1 + w[1] * q2 + w[2] * q3;
 }
 
 // Reverse of hweno_with: z = sum_l w_l q_l(f, s) with given weights. Adds the adjoints of the
@@ -156,13 +179,10 @@ __device__ __forceinline__ void interface_vjp(const NodeF<double> X[4], double a
   const double i4dx = 0.25 / dx, i12dx = K112 / dx;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    W3<double> a, b;
-    const double vp = hweno_side(fp[0][k], fp[1][k], fp[2][k], sp[0][k], sp[1][k], sp[2][k], eps, a);
-    const double vm = hweno_side(fm[3][k], fm[2][k], fm[1][k], -sm[3][k], -sm[2][k], -sm[1][k], eps, b);
-    wp[k][0] = a.w1; wp[k][1] = a.w2; wp[k][2] = a.w3;
-    wm[k][0] = b.w1; wm[k][1] = b.w2; wm[k][2] = b.w3;
+    const double vp = side_value(fp[0][k], fp[1][k], fp[2][k], sp[0][k], sp[1][k], sp[2][k], eps, wp[k]);
+    const double vm = side_value(fm[3][k], fm[2][k], fm[1][k], -sm[3][k], -sm[2][k], -sm[1][k], eps, wm[k]);
     s[k] = vp + vm;
-    Z[k] = hweno_with(bA, bB, bC, sbA, sbB, sbC, a) + hweno_with(bD, bC, bB, -sbD, -sbC, -sbB, b);
+    Z[k] = with_value(bA, bB, bC, sbA, sbB, sbC, wp[k]) + with_value(bD, bC, bB, -sbD, -sbC, -sbB, wm[k]);
     t[k] = ((fp[0][k] - fm[3][k]) + 8.0 * (fm[2][k] - fp[1][k]) + 7.0 * (fp[2][k] - fm[1][k])) * i4dx +
            ((sp[0][k] + sm[3][k]) - 2.0 * (sp[1][k] + sm[2][k]) - 5.0 * (sp[2][k] + sm[1][k])) * i12dx;
   }

@@ -17,6 +17,10 @@ enum { S_ETA = 0, S_M, S_W, S_H1, S_M1, S_W1, S_H2, S_M2, S_W2, S_B, S_BX, S_BY,
 // Constants of the reconstructions (Sec. 2.1 and 2.2).
 constexpr double K16 = 1.0 / 6.0, K112 = 1.0 / 12.0, K133 = 13.0 / 3.0, K1312 = 13.0 / 12.0;
 constexpr double K78120 = 781.0 / 20.0, K78180 = 781.0 / 80.0;
+// Square roots of the smoothness indicators' coefficients, folded into the differences:
+// 13/3, 781/20, 13/12, 781/80.
+constexpr double RA = 2.0816659994661326, RC = 6.248999919987197;
+constexpr double RB = 1.0408329997330663, RD = 3.1244999599935985;
 
 // Reciprocal for operands in the normal range: hardware estimate refined by two Newton steps
 // (error below one unit in the last place; the inputs here are depths, wave speeds and sums of
@@ -80,33 +84,39 @@ __device__ __forceinline__ void node_frame(const T* __restrict__ r, T g, NodeF<T
   o.b = b; o.bn = bn; o.bt = bt;
 }
 
+// Weights of one side up to a common factor (u_l) and the reciprocal of their sum.
 template <class T>
-struct W3 { T w1, w2, w3; };
+struct W3 { T u1, u2, u3, is; };
 
 // Upwind HWENO value at x_{i+1/2} from the stencil (i-1, i, i+1): f are split flux values,
 // s = dx * (split derivative-flux values). Smoothness indicators and candidate values of
-// Sec. 2.1; the weights gamma_l / (beta_l + eps)^2, normalised, are formed with one division as
-// gamma_1 e2 e3 : gamma_2 e1 e3 : gamma_3 e1 e2 with e_l = (beta_l + eps)^2.
+// Sec. 2.1. Each indicator is s1^2 + (k_a a)^2 + (k_c c)^2 with the square roots k of its
+// coefficients folded into the differences a, c. The weights gamma_l / (beta_l + eps)^2 are
+// kept unnormalised as gamma_1 e2 e3 : gamma_2 e1 e3 : gamma_3 e1 e2 (e_l = (beta_l + eps)^2,
+// scaled by 10/3) and the value is divided by their sum once.
 template <class T>
 __device__ __forceinline__ T hweno_side(T f0, T f1, T f2, T s0, T s1, T s2, T eps, W3<T>& w) {
   const T d01 = f0 - f1, d12 = f1 - f2;
   const T t = s1 * s1;
-  const T a1 = T(3.0) * d01 + s0 + T(2.0) * s1, c1 = T(2.0) * d01 + s0 + s1;
-  const T a2 = T(3.0) * d12 + s2 + T(2.0) * s1, c2 = T(2.0) * d12 + s2 + s1;
-  const T a3 = (f0 + f2) - T(2.0) * f1, c3 = (f0 - f2) + T(2.0) * s1;
-  const T be1 = t + T(K133) * (a1 * a1) + T(K78120) * (c1 * c1);
-  const T be2 = t + T(K133) * (a2 * a2) + T(K78120) * (c2 * c2);
-  const T be3 = t + T(K1312) * (a3 * a3) + T(K78180) * (c3 * c3);
-  const T e1 = (be1 + eps) * (be1 + eps);
-  const T e2 = (be2 + eps) * (be2 + eps);
-  const T e3 = (be3 + eps) * (be3 + eps);
-  const T u1 = T(0.3) * (e2 * e3), u2 = T(0.3) * (e1 * e3), u3 = T(0.4) * (e1 * e2);
-  const T is = rcp((u1 + u2) + u3);
-  w.w1 = u1 * is; w.w2 = u2 * is; w.w3 = u3 * is;
+  const T ra = T(2.0 * RA) * s1, rc = T(RC) * s1;
+  const T a1 = fma(T(3.0 * RA), d01, fma(T(RA), s0, ra));  // RA (3 d01 + s0 + 2 s1)
+  const T c1 = fma(T(2.0 * RC), d01, fma(T(RC), s0, rc));  // RC (2 d01 + s0 + s1)
+  const T a2 = fma(T(3.0 * RA), d12, fma(T(RA), s2, ra));  // RA (3 d12 + s2 + 2 s1)
+  const T c2 = fma(T(2.0 * RC), d12, fma(T(RC), s2, rc));  // RC (2 d12 + s2 + s1)
+  const T a3 = T(RB) * (d01 - d12);                         // RB (f0 - 2 f1 + f2)
+  const T c3 = fma(T(RD), d01 + d12, T(2.0 * RD) * s1);     // RD (f0 - f2 + 2 s1)
+  const T g1 = fma(a1, a1, fma(c1, c1, t)) + eps;
+  const T g2 = fma(a2, a2, fma(c2, c2, t)) + eps;
+  const T g3 = fma(a3, a3, fma(c3, c3, t)) + eps;
+  const T e1 = g1 * g1, e2 = g2 * g2, e3 = g3 * g3;
+  w.u1 = e2 * e3;
+  w.u2 = e1 * e3;
+  w.u3 = T(4.0 / 3.0) * (e1 * e2);
+  w.is = rcp((w.u1 + w.u2) + w.u3);
   const T q1 = T(0.5) * (f0 + f1) + T(K16) * (s0 + T(5.0) * s1);
   const T q2 = T(0.5) * (f1 + f2) + T(K16) * (s1 - s2);
   const T q3 = T(K112) * ((f0 + f2) + T(10.0) * f1) + T(0.5) * s1;
-  return w.w1 * q1 + w.w2 * q2 + w.w3 * q3;
+  return ((w.u1 * q1 + w.u2 * q2) + w.u3 * q3) * w.is;
 }
 
 // The three candidate values combined with given weights (the source split of Step 2).
@@ -115,7 +125,7 @@ __device__ __forceinline__ T hweno_with(T f0, T f1, T f2, T s0, T s1, T s2, cons
   const T q1 = T(0.5) * (f0 + f1) + T(K16) * (s0 + T(5.0) * s1);
   const T q2 = T(0.5) * (f1 + f2) + T(K16) * (s1 - s2);
   const T q3 = T(K112) * ((f0 + f2) + T(10.0) * f1) + T(0.5) * s1;
-  return w.w1 * q1 + w.w2 * q2 + w.w3 * q3;
+  return ((w.u1 * q1 + w.u2 * q2) + w.u3 * q3) * w.is;
 }
 
 // Interface quantities at x_{i+1/2}, frame order (eta, n, t).
@@ -146,44 +156,53 @@ __device__ __forceinline__ void interface_flux(Fetch fetch, T alpha, T dx, T eps
   const T cs = sqrt(g * h), i2c = T(0.5) * rcp(cs);
   const T l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
   // rows: l1 = (l1a, -i2c, 0), l2 = (-ut, 0, 1), l3 = (l3a, i2c, 0)
-  const T ha = T(0.5) * alpha, hdx = T(0.5) * dx, hadx = ha * dx;
+  // projected, split values f^± = L (F ± alpha U) / 2, s^± = dx L (P ± alpha D) / 2, formed from
+  // the split sums with the rows of L scaled by 1/2 (f) and dx/2 (s)
+  const T hl1 = T(0.5) * l1a, hl3 = T(0.5) * l3a, hi2 = T(0.5) * i2c, hut = T(0.5) * ut;
+  const T hdx = T(0.5) * dx;
+  const T sl1 = hdx * l1a, sl3 = hdx * l3a, si2 = hdx * i2c, sut = hdx * ut;
 
-  // projected, split values: f^± = (L F ± alpha L U)/2, s^± = dx (L P ± alpha L D)/2
   T fpA[3], spA[3], fpB[3], spB[3], fmB[3], smB[3], fpC[3], spC[3], fmC[3], smC[3], fmD[3], smD[3];
   T bA, bB, bC, bD, sbA, sbB, sbC, sbD;  // bottom and dx * its derivative along the sweep
   T q1s[4], q7s[4];                      // partial sums of the mixed four-point flux
-#define SWE_PROJ(X, FP, SP, FM, SM, PLUS, MINUS)                                                  \
-  {                                                                                               \
-    const T lf[3] = {l1a * X.f0 - i2c * X.f1, X.f2 - ut * X.f0, l3a * X.f0 + i2c * X.f1}; \
-    const T lu[3] = {l1a * X.e - i2c * X.mn, X.mt - ut * X.e, l3a * X.e + i2c * X.mn};    \
-    const T lp[3] = {l1a * X.p0 - i2c * X.p1, X.p2 - ut * X.p0, l3a * X.p0 + i2c * X.p1}; \
-    const T ld[3] = {l1a * X.d0 - i2c * X.d1, X.d2 - ut * X.d0, l3a * X.d0 + i2c * X.d1}; \
-    _Pragma("unroll") for (int k = 0; k < 3; ++k) {                                               \
-      if (PLUS) { FP[k] = T(0.5) * lf[k] + ha * lu[k]; SP[k] = hdx * lp[k] + hadx * ld[k]; }         \
-      if (MINUS) { FM[k] = T(0.5) * lf[k] - ha * lu[k]; SM[k] = hdx * lp[k] - hadx * ld[k]; }        \
-    }                                                                                             \
+#define SWE_PROJ(L1, L3, I2, UT, SG, V0, V1, V2, Y)   \
+  {                                                    \
+    const T p_ = I2 * (V1);                            \
+    Y[0] = fma(L1, V0, -p_);                           \
+    Y[1] = fma(-(UT), V0, SG * (V2));                  \
+    Y[2] = fma(L3, V0, p_);                            \
   }
-  T dummy[3];
-  SWE_PROJ(XB, fpB, spB, fmB, smB, true, true)
+#define SWE_SPLIT(X, SGN, FY, SY)                                                        \
+  {                                                                                      \
+    const T a_ = SGN * alpha;                                                            \
+    const T g0 = fma(a_, X.e, X.f0), g1 = fma(a_, X.mn, X.f1), g2 = fma(a_, X.mt, X.f2); \
+    SWE_PROJ(hl1, hl3, hi2, hut, T(0.5), g0, g1, g2, FY)                                 \
+    const T h0 = fma(a_, X.d0, X.p0), h1 = fma(a_, X.d1, X.p1), h2 = fma(a_, X.d2, X.p2); \
+    SWE_PROJ(sl1, sl3, si2, sut, hdx, h0, h1, h2, SY)                                    \
+  }
+  SWE_SPLIT(XB, T(1.0), fpB, spB)
+  SWE_SPLIT(XB, T(-1.0), fmB, smB)
   bB = XB.b; sbB = dx * XB.bn;
   q7s[0] = XB.q0; q7s[1] = XB.q1; q7s[2] = XB.q2; q7s[3] = XB.bt;
-  SWE_PROJ(XC, fpC, spC, fmC, smC, true, true)
+  SWE_SPLIT(XC, T(1.0), fpC, spC)
+  SWE_SPLIT(XC, T(-1.0), fmC, smC)
   bC = XC.b; sbC = dx * XC.bn;
   q7s[0] += XC.q0; q7s[1] += XC.q1; q7s[2] += XC.q2; q7s[3] += XC.bt;
   {
     NodeF<T> X;
     fetch(0, X);
-    SWE_PROJ(X, fpA, spA, dummy, dummy, true, false)
+    SWE_SPLIT(X, T(1.0), fpA, spA)
     bA = X.b; sbA = dx * X.bn;
     q1s[0] = X.q0; q1s[1] = X.q1; q1s[2] = X.q2; q1s[3] = X.bt;
   }
   {
     NodeF<T> X;
     fetch(3, X);
-    SWE_PROJ(X, dummy, dummy, fmD, smD, false, true)
+    SWE_SPLIT(X, T(-1.0), fmD, smD)
     bD = X.b; sbD = dx * X.bn;
     q1s[0] += X.q0; q1s[1] += X.q1; q1s[2] += X.q2; q1s[3] += X.bt;
   }
+#undef SWE_SPLIT
 #undef SWE_PROJ
 
   // nonlinear reconstruction per characteristic field and side; the bottom reuses the weights
@@ -239,7 +258,8 @@ __device__ __forceinline__ T limit_char(T mm, T m0, T mp, T nm, T np, T dx,
   const T be2 = a2 * a2 + T(K133) * (c2 * c2);
   const T be3 = a3 * a3 + T(K1312) * (c3 * c3);
   const T e1 = (be1 + eps) * (be1 + eps), e2 = (be2 + eps) * (be2 + eps), e3 = (be3 + eps) * (be3 + eps);
-  const T u1 = T(0.25) * (e2 * e3), u2 = T(0.25) * (e1 * e3), u3 = T(0.5) * (e1 * e2);
+  // weights (1/4, 1/4, 1/2) / e_l up to the common factor 4 / (e1 e2 e3)
+  const T u1 = e2 * e3, u2 = e1 * e3, u3 = T(2.0) * (e1 * e2);
   const T is = rcp((u1 + u2) + u3);
   return ((u1 * a1 + u2 * a2) + u3 * a3) * is * idx;
 }
