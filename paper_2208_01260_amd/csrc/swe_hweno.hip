@@ -133,6 +133,29 @@ __device__ __forceinline__ void nodef_load(T (*sn)[64], int l, NodeF<T>& X) {
   X.q0 = sn[12][l]; X.q1 = sn[13][l]; X.q2 = sn[14][l]; X.b = sn[15][l]; X.bn = sn[16][l]; X.bt = sn[17][l];
 }
 
+// y-frame node fluxes kept per row: the six values of a NodeF that are not raw record slots
+// (F1, F2, P1, P2, Q1, Q2), in a ring of four rows of the march (own lane only).
+template <class T>
+__device__ __forceinline__ void yring_store(T (*ring)[6][WAVE], int row, int lane, const T* __restrict__ r, T g) {
+  NodeF<T> X;
+  node_frame<1>(r, g, X);
+  const int s = row & 3;
+  ring[s][0][lane] = X.f1; ring[s][1][lane] = X.f2;
+  ring[s][2][lane] = X.p1; ring[s][3][lane] = X.p2;
+  ring[s][4][lane] = X.q1; ring[s][5][lane] = X.q2;
+}
+template <class T>
+__device__ __forceinline__ void yring_load(T (*ring)[6][WAVE], int row, int lane, const T* __restrict__ r,
+                                           NodeF<T>& X) {
+  const int s = row & 3;
+  X.e = r[S_ETA]; X.mn = r[S_W]; X.mt = r[S_M];
+  X.d0 = r[S_H2]; X.d1 = r[S_W2]; X.d2 = r[S_M2];
+  X.f0 = X.mn; X.f1 = ring[s][0][lane]; X.f2 = ring[s][1][lane];
+  X.p0 = X.d1; X.p1 = ring[s][2][lane]; X.p2 = ring[s][3][lane];
+  X.q0 = r[S_W1]; X.q1 = ring[s][4][lane]; X.q2 = ring[s][5][lane];
+  X.b = r[S_B]; X.bn = r[S_BY]; X.bt = r[S_BX];
+}
+
 template <class T>
 __device__ __forceinline__ void ifo_to_array(const IfO<T>& o, T* v) {
   v[0] = o.F0; v[1] = o.F1; v[2] = o.F2; v[3] = o.B0; v[4] = o.B1; v[5] = o.B2; v[6] = o.P0;
@@ -204,6 +227,7 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
   __shared__ T sn[NNODE][WAVE];  // x-frame fluxes of the current row, one node per lane
   __shared__ T sf[14][WAVE];     // x-interface quantities (lane l: interface left of its column)
   __shared__ T sy[14][WAVE];     // y-interface quantities of the previous row (own lane)
+  __shared__ T syf[4][6][WAVE];  // y-frame fluxes of rows r-1 .. r+2 (own lane)
   const int lane = threadIdx.x;
   const int c = tx * OUT_COLS - 2 + lane;  // this lane's column
   const int r0 = DIM == 2 ? ty * a.rows : 0;
@@ -226,9 +250,13 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
     load_rec<DIM>(a, a.S, c, r0 - 1, wm1);
     load_rec<DIM>(a, a.S, c, r0, w0);
     load_rec<DIM>(a, a.S, c, r0 + 1, wp1);
+    yring_store(syf, r0 - 2, lane, wm2, a.g);
+    yring_store(syf, r0 - 1, lane, wm1, a.g);
+    yring_store(syf, r0, lane, w0, a.g);
+    yring_store(syf, r0 + 1, lane, wp1, a.g);
     IfO<T> o;
     auto fy = [&](int k, NodeF<T>& X) {
-      node_frame<1>(k == 0 ? wm2 : (k == 1 ? wm1 : (k == 2 ? w0 : wp1)), a.g, X);
+      yring_load(syf, r0 - 2 + k, lane, k == 0 ? wm2 : (k == 1 ? wm1 : (k == 2 ? w0 : wp1)), X);
     };
     interface_flux(fy, ayl, a.dy, a.eps, a.g, o);
     T v[14];
@@ -282,8 +310,9 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
     // y-sweep: interface r+1/2 from rows r-1 .. r+2
     if (DIM == 2) {
       IfO<T> o;
+      yring_store(syf, r + 2, lane, wp2, a.g);
       auto fy = [&](int k, NodeF<T>& X) {
-        node_frame<1>(k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2)), a.g, X);
+        yring_load(syf, r - 1 + k, lane, k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2)), X);
       };
       interface_flux(fy, ayl, a.dy, a.eps, a.g, o);
       T ynew[14], yprev[14];
