@@ -91,13 +91,14 @@ struct W3 { T u1, u2, u3, is; };
 // Upwind HWENO value at x_{i+1/2} from the stencil (i-1, i, i+1): f are split flux values,
 // s = dx * (split derivative-flux values). Smoothness indicators and candidate values of
 // Sec. 2.1. Each indicator is s1^2 + (k_a a)^2 + (k_c c)^2 with the square roots k of its
-// coefficients folded into the differences a, c. The weights gamma_l / (beta_l + eps)^2 are
-// kept unnormalised as gamma_1 e2 e3 : gamma_2 e1 e3 : gamma_3 e1 e2 (e_l = (beta_l + eps)^2,
-// scaled by 10/3) and the value is divided by their sum once.
+// coefficients folded into the differences a, c (and eps added to the shared s1^2). The weights
+// gamma_l / (beta_l + eps)^2 are kept unnormalised as gamma_1 e2 e3 : gamma_2 e1 e3 : gamma_3 e1 e2
+// (e_l = (beta_l + eps)^2, scaled by 10/3); the candidates are formed doubled, and the value is
+// divided once by twice the weights' sum.
 template <class T>
 __device__ __forceinline__ T hweno_side(T f0, T f1, T f2, T s0, T s1, T s2, T eps, W3<T>& w) {
   const T d01 = f0 - f1, d12 = f1 - f2;
-  const T t = s1 * s1;
+  const T te = fma(s1, s1, eps);
   const T ra = T(2.0 * RA) * s1, rc = T(RC) * s1;
   const T a1 = fma(T(3.0 * RA), d01, fma(T(RA), s0, ra));  // RA (3 d01 + s0 + 2 s1)
   const T c1 = fma(T(2.0 * RC), d01, fma(T(RC), s0, rc));  // RC (2 d01 + s0 + s1)
@@ -105,26 +106,28 @@ __device__ __forceinline__ T hweno_side(T f0, T f1, T f2, T s0, T s1, T s2, T ep
   const T c2 = fma(T(2.0 * RC), d12, fma(T(RC), s2, rc));  // RC (2 d12 + s2 + s1)
   const T a3 = T(RB) * (d01 - d12);                         // RB (f0 - 2 f1 + f2)
   const T c3 = fma(T(RD), d01 + d12, T(2.0 * RD) * s1);     // RD (f0 - f2 + 2 s1)
-  const T g1 = fma(a1, a1, fma(c1, c1, t)) + eps;
-  const T g2 = fma(a2, a2, fma(c2, c2, t)) + eps;
-  const T g3 = fma(a3, a3, fma(c3, c3, t)) + eps;
+  const T g1 = fma(a1, a1, fma(c1, c1, te));
+  const T g2 = fma(a2, a2, fma(c2, c2, te));
+  const T g3 = fma(a3, a3, fma(c3, c3, te));
   const T e1 = g1 * g1, e2 = g2 * g2, e3 = g3 * g3;
   w.u1 = e2 * e3;
   w.u2 = e1 * e3;
   w.u3 = T(4.0 / 3.0) * (e1 * e2);
-  w.is = rcp((w.u1 + w.u2) + w.u3);
-  const T q1 = T(0.5) * (f0 + f1) + T(K16) * (s0 + T(5.0) * s1);
-  const T q2 = T(0.5) * (f1 + f2) + T(K16) * (s1 - s2);
-  const T q3 = T(K112) * ((f0 + f2) + T(10.0) * f1) + T(0.5) * s1;
+  const T su = (w.u1 + w.u2) + w.u3;
+  w.is = rcp(su + su);
+  // doubled candidates: 2 q_l
+  const T q1 = fma(T(1.0 / 3.0), fma(T(5.0), s1, s0), f0 + f1);
+  const T q2 = fma(T(1.0 / 3.0), s1 - s2, f1 + f2);
+  const T q3 = fma(T(1.0 / 6.0), fma(T(10.0), f1, f0 + f2), s1);
   return ((w.u1 * q1 + w.u2 * q2) + w.u3 * q3) * w.is;
 }
 
 // The three candidate values combined with given weights (the source split of Step 2).
 template <class T>
 __device__ __forceinline__ T hweno_with(T f0, T f1, T f2, T s0, T s1, T s2, const W3<T>& w) {
-  const T q1 = T(0.5) * (f0 + f1) + T(K16) * (s0 + T(5.0) * s1);
-  const T q2 = T(0.5) * (f1 + f2) + T(K16) * (s1 - s2);
-  const T q3 = T(K112) * ((f0 + f2) + T(10.0) * f1) + T(0.5) * s1;
+  const T q1 = fma(T(1.0 / 3.0), fma(T(5.0), s1, s0), f0 + f1);
+  const T q2 = fma(T(1.0 / 3.0), s1 - s2, f1 + f2);
+  const T q3 = fma(T(1.0 / 6.0), fma(T(10.0), f1, f0 + f2), s1);
   return ((w.u1 * q1 + w.u2 * q2) + w.u3 * q3) * w.is;
 }
 
@@ -254,10 +257,10 @@ __device__ __forceinline__ T limit_char(T mm, T m0, T mp, T nm, T np, T dx,
   const T a2 = T(2.0) * (mp - m0) - np * dx;       // dx * p2'(x_i)
   const T a3 = T(0.5) * (mp - mm);                 // dx * p3'(x_i)
   const T c1 = (m0 - mm) - nm * dx, c2 = (mp - m0) - np * dx, c3 = (mm + mp) - T(2.0) * m0;
-  const T be1 = a1 * a1 + T(K133) * (c1 * c1);
-  const T be2 = a2 * a2 + T(K133) * (c2 * c2);
-  const T be3 = a3 * a3 + T(K1312) * (c3 * c3);
-  const T e1 = (be1 + eps) * (be1 + eps), e2 = (be2 + eps) * (be2 + eps), e3 = (be3 + eps) * (be3 + eps);
+  const T g1 = fma(a1, a1, fma(T(K133) * c1, c1, eps));
+  const T g2 = fma(a2, a2, fma(T(K133) * c2, c2, eps));
+  const T g3 = fma(a3, a3, fma(T(K1312) * c3, c3, eps));
+  const T e1 = g1 * g1, e2 = g2 * g2, e3 = g3 * g3;
   // weights (1/4, 1/4, 1/2) / e_l up to the common factor 4 / (e1 e2 e3)
   const T u1 = e2 * e3, u2 = e1 * e3, u3 = T(2.0) * (e1 * e2);
   const T is = rcp((u1 + u2) + u3);
