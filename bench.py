@@ -117,8 +117,10 @@ def single_precision(args, torch, pr, f_rhs):
 
 def adjoint_cost(args, torch):
     """Reverse mode on the adjoint workload: 256^2, 100 steps at a fixed dt with frozen speeds,
-    checkpoint every 10 steps. Cost = swe_hweno_run_vjp (checkpointed forward, recomputation and
-    reverse) over the plain forward run of the same steps."""
+    checkpoint every 10 steps. Reported against the plain forward run of the same steps:
+    swe_hweno_run_vjp (its own checkpointed forward, recomputation and reverse), and the
+    autograd split: swe_hweno_run_checkpointed (forward keeping checkpoints) and
+    swe_hweno_run_vjp_checkpointed (recomputation and reverse)."""
     from paper_2208_01260_amd import inputs
     from paper_2208_01260_amd.solver import FIXED_ALPHA, FIXED_DT, Solver
 
@@ -129,28 +131,39 @@ def adjoint_cost(args, torch):
         ax, ay = s.alpha(st0)
     al = (1.1 * ax, 1.1 * ay)
     dt = 0.6 / (al[0] / pr.dx + al[1] / pr.dy)
+    reps = 3
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
     with Solver.from_problem(pr, flags=FIXED_DT | FIXED_ALPHA, fixed_dt=dt, alpha=al) as s:
         st = st0.clone()
-        s.run(st, nsteps=nsteps)
         sbar = torch.randn_like(st0)
-        s.run_vjp(st0, nsteps, sbar, ck)
-        torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
+
+        def fwd():
             st.copy_(st0)
             s.run(st, nsteps=nsteps)
-        torch.cuda.synchronize()
-        fwd = (time.perf_counter() - t0) / reps
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            s.run_vjp(st0, nsteps, sbar, ck)
-        torch.cuda.synchronize()
-        bwd = (time.perf_counter() - t0) / reps
-    print(f"[bench] adjoint: forward {fwd * 1e3:.2f} ms, reverse {bwd * 1e3:.2f} ms ({bwd / fwd:.2f}x)",
+
+        def fwd_ck():
+            st.copy_(st0)
+            s.run_checkpointed(st, nsteps, ck)
+
+        fwd_ms = timed(fwd)
+        vjp_ms = timed(lambda: s.run_vjp(st0, nsteps, sbar, ck))
+        fwd_ck_ms = timed(fwd_ck)
+        bwd_ms = timed(lambda: s.run_vjp_checkpointed(nsteps, sbar, ck))
+    print(f"[bench] adjoint: forward {fwd_ms:.2f} ms, run_vjp {vjp_ms:.2f} ms ({vjp_ms / fwd_ms:.2f}x); "
+          f"checkpointed forward {fwd_ck_ms:.2f} ms, backward {bwd_ms:.2f} ms ({bwd_ms / fwd_ms:.2f}x)",
           file=sys.stderr, flush=True)
-    return {"workload": "256x256, 100 steps, fixed dt, frozen alpha, checkpoint every 10", "forward_ms": fwd * 1e3,
-            "reverse_ms": bwd * 1e3, "reverse_over_forward": bwd / fwd}
+    return {"workload": "256x256, 100 steps, fixed dt, frozen alpha, checkpoint every 10", "forward_ms": fwd_ms,
+            "run_vjp_ms": vjp_ms, "run_vjp_over_forward": vjp_ms / fwd_ms,
+            "checkpointed_forward_ms": fwd_ck_ms, "backward_ms": bwd_ms, "backward_over_forward": bwd_ms / fwd_ms}
 
 
 def batched(args, torch):

@@ -231,6 +231,17 @@ int swe_hweno_limit_vjp(swe_hweno_ctx* ctx, const double* state, const double* d
 int swe_hweno_run_vjp(swe_hweno_ctx* ctx, const double* state0, int nsteps, int checkpoint_every,
                       const double* sbar_T, double* sbar_0, double* bbar, double* bxbar, double* bybar);
 
+/* The same reverse in two halves, for callers that run the forward themselves (an autograd
+ * forward): swe_hweno_run_checkpointed advances state in place by nsteps steps (as
+ * swe_hweno_run; same flags required) and keeps the states at the start of every
+ * checkpoint_every steps in the context; swe_hweno_run_vjp_checkpointed then runs the reverse
+ * of that run from those checkpoints (nsteps and checkpoint_every must match, else SWE_EINVAL;
+ * any other adjoint call on the context in between discards them). Outputs as for
+ * swe_hweno_run_vjp. */
+int swe_hweno_run_checkpointed(swe_hweno_ctx* ctx, double* state, int nsteps, int checkpoint_every);
+int swe_hweno_run_vjp_checkpointed(swe_hweno_ctx* ctx, int nsteps, int checkpoint_every, const double* sbar_T,
+                                   double* sbar_0, double* bbar, double* bxbar, double* bybar);
+
 /* Bottom slopes by the fourth-order centred difference
  *   bx_i = (b_{i-2} - 8 b_{i-1} + 8 b_{i+1} - b_{i+2}) / (12 dx)   (by likewise along y),
  * with b extended through the boundary (periodic wrap, or even about a reflective wall), for

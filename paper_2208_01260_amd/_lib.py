@@ -27,7 +27,7 @@ EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alph
            "swe_hweno_init_f32", "swe_hweno_rhs_f32", "swe_hweno_limit_f32", "swe_hweno_alpha_f32",
            "swe_hweno_step_f32", "swe_hweno_run_f32",
            "swe_hweno_rhs_vjp", "swe_hweno_limit_vjp", "swe_hweno_run_vjp", "swe_hweno_bottom_slopes",
-           "swe_hweno_bottom_slopes_vjp")
+           "swe_hweno_bottom_slopes_vjp", "swe_hweno_run_checkpointed", "swe_hweno_run_vjp_checkpointed")
 
 
 class SweError(RuntimeError):
@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_limit_vjp": (I, [vp, dp, dp, dp, dp]),
         "swe_hweno_run_vjp": (I, [vp, dp, I, I, dp, dp, dp, dp, dp]),
         "swe_hweno_bottom_slopes": (I, [P, dp, dp, dp, vp]),
+        "swe_hweno_run_checkpointed": (I, [vp, dp, I, I]),
+        "swe_hweno_run_vjp_checkpointed": (I, [vp, I, I, dp, dp, dp, dp, dp]),
         "swe_hweno_bottom_slopes_vjp": (I, [P, dp, dp, dp, vp]),
         "swe_hweno_sync": (I, [vp]),
         "swe_hweno_destroy": (None, [vp]),

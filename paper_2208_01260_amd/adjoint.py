@@ -1,5 +1,6 @@
 """Differentiable runs of the 2D scheme: a torch.autograd.Function over the library's forward
-run and its hand-written reverse (swe_hweno_run_vjp).
+run (swe_hweno_run_checkpointed, which keeps checkpoints) and its hand-written reverse
+(swe_hweno_run_vjp_checkpointed).
 
 The run is taken at a fixed dt with the Lax-Friedrichs speeds frozen (the map is then smooth).
 The bottom enters through b alone: its slopes are b_x, b_y = D(b) by the library's fixed
@@ -58,16 +59,14 @@ class SWERun(torch.autograd.Function):
         s = Solver(2, nx, ny, domain, b, bx, by, bc=bc, g=g, cfl=cfl, eps=eps, flags=FIXED_DT | FIXED_ALPHA,
                    fixed_dt=dt, alpha=alpha)
         st = state0.detach().clone()
-        s.run(st, nsteps=nsteps)
+        s.run_checkpointed(st, nsteps, checkpoint_every)
         ctx.solver, ctx.nsteps, ctx.ck, ctx.domain, ctx.bc = s, nsteps, checkpoint_every, domain, bc
-        ctx.save_for_backward(state0)
         return st
 
     @staticmethod
     def backward(ctx, grad_out):
-        (state0,) = ctx.saved_tensors
         s = ctx.solver
-        sbar0, bb, bxb, byb = s.run_vjp(state0.detach().contiguous(), ctx.nsteps, grad_out.contiguous(), ctx.ck)
+        sbar0, bb, bxb, byb = s.run_vjp_checkpointed(ctx.nsteps, grad_out.contiguous(), ctx.ck)
         bottom_slopes_vjp(bxb, byb, bb, ctx.domain, ctx.bc)
         s.close()
         return sbar0, bb, None, None, None, None, None, None, None, None, None

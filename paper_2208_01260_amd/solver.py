@@ -140,6 +140,22 @@ class Solver:
                                                bb.data_ptr()), "swe_hweno_limit_vjp")
         return sbar, bb
 
+    def run_checkpointed(self, state, nsteps, checkpoint_every=10):
+        """nsteps fixed-dt, frozen-alpha steps of state in place, keeping checkpoints for
+        run_vjp_checkpointed."""
+        _lib.check(self._L.swe_hweno_run_checkpointed(self._ctx, self._state(state), int(nsteps),
+                                                      int(checkpoint_every)), "swe_hweno_run_checkpointed")
+
+    def run_vjp_checkpointed(self, nsteps, sbar_T, checkpoint_every=10):
+        """Reverse of the last run_checkpointed: (sbar_0, bbar, bxbar, bybar)."""
+        sbar0 = torch.empty_like(sbar_T)
+        bb, bxb, byb = self._planes(), self._planes(), self._planes()
+        _lib.check(self._L.swe_hweno_run_vjp_checkpointed(self._ctx, int(nsteps), int(checkpoint_every),
+                                                          self._state(sbar_T, "sbar_T"), sbar0.data_ptr(),
+                                                          bb.data_ptr(), bxb.data_ptr(), byb.data_ptr()),
+                   "swe_hweno_run_vjp_checkpointed")
+        return sbar0, bb, bxb, byb
+
     def run_vjp(self, state0, nsteps, sbar_T, checkpoint_every=10):
         """Reverse of `nsteps` fixed-dt, frozen-alpha steps from state0: returns
         (sbar_0, bbar, bxbar, bybar) for the adjoint sbar_T of the final state."""

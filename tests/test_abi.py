@@ -101,6 +101,13 @@ def test_null_arguments_rejected(L):
     assert L.swe_hweno_step_f32(None, None, 0.0, None) == -1
     assert L.swe_hweno_run_f32(None, None, 1, 0.0, None, None) == -1
     assert L.swe_hweno_alpha_f32(None, None, None) == -1
+    assert L.swe_hweno_rhs_vjp(None, None, 1.0, 1.0, None, None, None, None, None) == -1
+    assert L.swe_hweno_limit_vjp(None, None, None, None, None) == -1
+    assert L.swe_hweno_run_vjp(None, None, 1, 1, None, None, None, None, None) == -1
+    assert L.swe_hweno_run_checkpointed(None, None, 1, 1) == -1
+    assert L.swe_hweno_run_vjp_checkpointed(None, 1, 1, None, None, None, None, None) == -1
+    assert L.swe_hweno_bottom_slopes(None, None, None, None, None) == -1
+    assert L.swe_hweno_bottom_slopes_vjp(None, None, None, None, None) == -1
 
 
 def test_batch_init_rejects_bad_arguments(L):

@@ -180,6 +180,17 @@ def test_run_vjp_against_oracle_tangent(oracle_mod, inputs_mod, torch_cuda, limi
         for r in res[1:]:  # the checkpoint interval changes nothing
             for x, y in zip(res[0], r):
                 assert np.array_equal(x, y)
+        # the two-call form (checkpoints kept by the forward run) gives the same bits
+        from paper_2208_01260_amd.solver import SweError
+
+        with Solver.from_problem(pr, flags=flags, fixed_dt=dt, alpha=al) as s:
+            st = dev(torch, pr.state)
+            s.run_checkpointed(st, nsteps, 5)
+            with pytest.raises(SweError):
+                s.run_vjp_checkpointed(nsteps + 1, dev(torch, sT_bar), 5)
+            r2 = [host(t) for t in s.run_vjp_checkpointed(nsteps, dev(torch, sT_bar), 5)]
+            for x, y in zip(res[0], r2):
+                assert np.array_equal(x, y)
         sb0, bb, bxb, byb = res[0]
         ds, db, dbx, dby = directions(pr, rng)
 
