@@ -160,7 +160,7 @@ int swe_hweno_ctx_tile(const swe_hweno_ctx* ctx, int* cols_per_wave, int* rows_p
  * from captured HIP graphs of at most 16 steps. Each step is the one swe_hweno_step takes (the
  * scheme of Sec. 2 and 3 of the paper: SSP-RK3 stages, each a full right-hand side, limiter and
  * update). Each instance's result is bitwise the result of the plain solver on the same
- * instance with the same rows per march: the batch tiling changes no arithmetic.
+ * instance with the same rows per march: the batch tiling changes no arithmetic. FP64 only.
  * ------------------------------------------------------------------------------------------ */
 typedef struct swe_hweno_batch swe_hweno_batch; /* opaque, owned by the library */
 
@@ -208,8 +208,10 @@ void swe_hweno_batch_destroy(swe_hweno_batch* bt);
  * of the limiter (Sec. 2.2, eq. (2.13)) and of a run of SSP-RK3 steps (eq. (2.11)) at a fixed dt.
  * The bottom b and its slopes bx, by enter as independent inputs; swe_hweno_bottom_slopes and
  * its transpose tie them together when the gradient with respect to b alone is wanted. Work
- * buffers (about 230 planes at a checkpoint interval of 10, plus the checkpoints) are allocated
- * on first use and kept with the context. All arrays are DEVICE arrays; outputs are overwritten.
+ * buffers are allocated on first use and kept with the context until swe_hweno_destroy: about
+ * 170 planes of nx*ny doubles, plus 27 per step of the checkpoint interval (the recomputed stage
+ * states of one segment) and 9 per checkpoint. All arrays are DEVICE arrays; outputs are
+ * overwritten. FP64 contexts only (an FP32 context returns SWE_EINVAL).
  * ------------------------------------------------------------------------------------------ */
 
 /* rbar (state layout) is the adjoint of R(state) with alpha = (alpha_x, alpha_y) > 0 fixed.
