@@ -238,7 +238,7 @@ int swe_hweno_run_vjp(swe_hweno_ctx* ctx, const double* state0, int nsteps, int 
  * swe_hweno_run; same flags required) and keeps the states at the start of every
  * checkpoint_every steps in the context; swe_hweno_run_vjp_checkpointed then runs the reverse
  * of that run from those checkpoints (nsteps and checkpoint_every must match, else SWE_EINVAL;
- * any other adjoint call on the context in between discards them). Outputs as for
+ * a swe_hweno_run_vjp call on the context in between discards them). Outputs as for
  * swe_hweno_run_vjp. */
 int swe_hweno_run_checkpointed(swe_hweno_ctx* ctx, double* state, int nsteps, int checkpoint_every);
 int swe_hweno_run_vjp_checkpointed(swe_hweno_ctx* ctx, int nsteps, int checkpoint_every, const double* sbar_T,
