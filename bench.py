@@ -56,6 +56,34 @@ def measured_traffic(workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def device_ceilings(torch, dev):
+    """What this device sustains, measured live beside the published peaks: a dense FP64 FMA
+    stream (two wavefronts per SIMD, about 0.6 s of back-to-back launches) and a device-to-device
+    copy of 2 GiB (bytes read + written per second)."""
+    from paper_2208_01260_amd.calib import fp64_fma_ceiling
+
+    tfl, mhz = fp64_fma_ceiling(2, 0.6)
+    n = (1 << 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    print(f"[bench] device ceilings: FP64 FMA stream {tfl:.1f} TFLOP/s at {mhz:.0f} MHz, copy {copy_gbs:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    return {"fp64_fma_stream_tflops": tfl, "fp64_fma_stream_shader_mhz": mhz, "copy_GBs": copy_gbs,
+            "fp64_fma_stream_frac_of_peak": tfl * 1e12 / PEAK_FP64, "copy_frac_of_hbm_peak": copy_gbs / 8000.0}
+
+
 def flop_counts():
     """Algorithmic flops per node (right-hand side, limiter), counted by the oracle's
     operation-counting scalar and stored by tests/golden/make_flop_counts.py."""
@@ -221,6 +249,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-loop", type=int, default=64, help="instances timed one by one for comparison")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured device ceilings (FP64 FMA stream, device copy)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
@@ -329,6 +359,11 @@ def main():
         "cell_steps_per_s": cells * args.steps / wall,
     }
     s.close()
+    if not args.no_ceilings:
+        line["device_ceilings"] = device_ceilings(torch, dev)
+        fma = line["device_ceilings"]["fp64_fma_stream_tflops"]
+        roof["frac_of_fp64_fma_stream"] = achieved / 1e12 / fma
+        rhs_kernel["frac_of_fp64_fma_stream"] = rhs_kernel["tflops"] / fma
     if not args.no_fp32:
         line["fp32"] = single_precision(args, torch, pr, f_rhs)
     if args.batch_count > 0:

@@ -9,6 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "swe_hweno.hip")
 OUT = os.path.join(HERE, "libswe_hweno.so")
+CALIB_SRC = os.path.join(HERE, "csrc", "calib.hip")
+CALIB_OUT = os.path.join(HERE, "libswe_hweno_calib.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -19,19 +21,25 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, out: str = OUT, defines=()) -> str:
-    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + [SRC, "-o", out + ".tmp"]
+def build(verbose: bool = False, out: str = OUT, defines=(), src: str = SRC) -> str:
+    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + [src, "-o", out + ".tmp"]
     if verbose:
         cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for " + SRC)
+        raise RuntimeError("hipcc failed for " + src)
     if verbose:
         sys.stderr.write(r.stderr)
     os.replace(out + ".tmp", out)
     return out
 
 
+def build_calib(verbose: bool = False) -> str:
+    """The device calibration library (sustained FP64 FMA stream) used by bench.py."""
+    return build(verbose, out=CALIB_OUT, src=CALIB_SRC)
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    print(build_calib(verbose="-v" in sys.argv))

@@ -135,3 +135,15 @@ def test_product_path_has_no_cpu_fallback():
     src += open(os.path.join(ROOT, "paper_2208_01260_amd", "_lib.py")).read()
     assert "oracle" not in src
     assert "import numpy" not in src
+
+
+def test_calibration_library_loads_and_checks_arguments():
+    """The device calibration used by bench.py (sustained FP64 FMA stream) is built in-tree and
+    rejects bad arguments on the host, before any device call."""
+    from paper_2208_01260_amd import calib
+
+    L = calib._load()
+    t, m = ctypes.c_double(), ctypes.c_double()
+    assert L.swe_calib_fp64_fma(3, 0.5, ctypes.byref(t), ctypes.byref(m)) == -1
+    assert L.swe_calib_fp64_fma(2, 0.0, ctypes.byref(t), ctypes.byref(m)) == -1
+    assert L.swe_calib_fp64_fma(2, 0.5, None, ctypes.byref(m)) == -1
