@@ -191,9 +191,16 @@ int swe_hweno_batch_run(swe_hweno_batch* bt, int nsteps, double* t_out);
 
 /* Rows per wavefront march of the batch kernels (>= 1); swe_hweno_batch_autotune times the
  * fused kernel on the batch's own data for a set of candidates (into scratch buffers, the
- * states are not touched), keeps the fastest and returns it. */
+ * states are not touched), keeps the fastest and returns it. The choice is cached for the life
+ * of the process per size class: the device's architecture and compute-unit count and
+ * power-of-two buckets of the instance count, the total nodes and the largest instance width
+ * and height. A batch of a class already tuned takes the cached rows without timing. The cache
+ * is shared by all threads (guarded by a mutex); tune_cache_size counts its entries and
+ * tune_cache_clear empties it (host-only, no HIP call). */
 int swe_hweno_batch_set_rows(swe_hweno_batch* bt, int rows);
 int swe_hweno_batch_autotune(swe_hweno_batch* bt, int* rows_out);
+int swe_hweno_batch_tune_cache_size(void);
+void swe_hweno_batch_tune_cache_clear(void);
 
 /* Synchronise and report (and clear) device-detected errors of any instance. */
 int swe_hweno_batch_sync(swe_hweno_batch* bt);

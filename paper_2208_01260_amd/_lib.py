@@ -23,7 +23,8 @@ EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alph
            "swe_hweno_run", "swe_hweno_sync", "swe_hweno_destroy", "swe_hweno_strerror", "swe_hweno_abi_version",
            "swe_hweno_tile", "swe_hweno_set_timing", "swe_hweno_get_timing", "swe_hweno_ctx_tile",
            "swe_hweno_batch_init", "swe_hweno_batch_run", "swe_hweno_batch_set_rows", "swe_hweno_batch_autotune",
-           "swe_hweno_batch_sync", "swe_hweno_batch_destroy",
+           "swe_hweno_batch_sync", "swe_hweno_batch_destroy", "swe_hweno_batch_tune_cache_size",
+           "swe_hweno_batch_tune_cache_clear",
            "swe_hweno_init_f32", "swe_hweno_rhs_f32", "swe_hweno_limit_f32", "swe_hweno_alpha_f32",
            "swe_hweno_step_f32", "swe_hweno_run_f32",
            "swe_hweno_rhs_vjp", "swe_hweno_limit_vjp", "swe_hweno_run_vjp", "swe_hweno_bottom_slopes",
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_batch_set_rows": (I, [vp, I]),
         "swe_hweno_batch_autotune": (I, [vp, ctypes.POINTER(I)]),
         "swe_hweno_batch_sync": (I, [vp]),
+        "swe_hweno_batch_tune_cache_size": (I, []),
+        "swe_hweno_batch_tune_cache_clear": (None, []),
         "swe_hweno_batch_destroy": (None, [vp]),
         "swe_hweno_get_timing": (I, [vp, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
     }

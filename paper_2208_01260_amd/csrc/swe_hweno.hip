@@ -24,6 +24,10 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "hweno_adjoint.hpp"

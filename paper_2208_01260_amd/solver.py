@@ -241,9 +241,18 @@ class Batch:
         _lib.check(self._L.swe_hweno_batch_set_rows(self._h, int(rows)), "swe_hweno_batch_set_rows")
 
     def autotune(self):
+        """Rows per march for this batch: timed, or taken from the process-wide cache of its size class."""
         r = ctypes.c_int()
         _lib.check(self._L.swe_hweno_batch_autotune(self._h, ctypes.byref(r)), "swe_hweno_batch_autotune")
         return r.value
+
+    @staticmethod
+    def tune_cache_size():
+        return _lib.lib().swe_hweno_batch_tune_cache_size()
+
+    @staticmethod
+    def tune_cache_clear():
+        _lib.lib().swe_hweno_batch_tune_cache_clear()
 
     def sync(self):
         _lib.check(self._L.swe_hweno_batch_sync(self._h), "swe_hweno_batch_sync")

@@ -94,6 +94,8 @@ def test_null_arguments_rejected(L):
     assert L.swe_hweno_batch_set_rows(None, 8) == -1
     assert L.swe_hweno_batch_autotune(None, None) == -1
     assert L.swe_hweno_batch_sync(None) == -1
+    L.swe_hweno_batch_tune_cache_clear()  # host-only
+    assert L.swe_hweno_batch_tune_cache_size() == 0
     L.swe_hweno_batch_destroy(None)
     assert L.swe_hweno_init_f32(ctypes.byref(p), None, None, None, None, ctypes.byref(ctx)) == -1
     assert L.swe_hweno_rhs_f32(None, None, None, -1.0, -1.0) == -1

@@ -97,9 +97,11 @@ def test_batch_rows_and_autotune_keep_results(inputs_mod, torch_cuda):
             bt.run(5)
             for i, s in enumerate(bt.states):
                 assert np.array_equal(s.cpu().numpy(), plain_run(torch, probs[i], 5, rows)[0]), (rows, i)
+    Batch.tune_cache_clear()
     with Batch(probs) as bt:
         r = bt.autotune()
         note(f"[batch] autotune chose {r}")
+        assert Batch.tune_cache_size() == 1
         assert r in (8, 12, 16, 24, 32, 48, 64)
         bt.run(5)
         for i, s in enumerate(bt.states):
@@ -108,6 +110,31 @@ def test_batch_rows_and_autotune_keep_results(inputs_mod, torch_cuda):
         bt.run(5)
         for i, pr in enumerate(probs):
             assert np.array_equal(bt.states[i].cpu().numpy(), plain_run(torch, pr, 10, r)[0]), i
+
+
+def test_batch_autotune_cache(inputs_mod, torch_cuda):
+    """A batch of a size class already tuned takes the cached rows; another class is tuned anew."""
+    from paper_2208_01260_amd.solver import Batch
+
+    torch = torch_cuda
+    probs = ragged_instances(inputs_mod)[:4]
+    Batch.tune_cache_clear()
+    assert Batch.tune_cache_size() == 0
+    with Batch(probs) as bt:
+        r = bt.autotune()
+    # the same instances in reverse order: same count, total nodes and extents
+    with Batch(probs[::-1]) as bt:
+        assert bt.autotune() == r
+        assert Batch.tune_cache_size() == 1
+        bt.run(3)
+        for i, pr in enumerate(probs[::-1]):
+            assert np.array_equal(bt.states[i].cpu().numpy(), plain_run(torch, pr, 3, r)[0]), i
+    # one instance only: another class
+    with Batch(probs[:1]) as bt:
+        bt.autotune()
+        assert Batch.tune_cache_size() == 2
+    Batch.tune_cache_clear()
+    assert Batch.tune_cache_size() == 0
 
 
 def test_batch_rows_change_rounding_only(inputs_mod, torch_cuda):

@@ -296,3 +296,76 @@ def test_c3_full_size_rhs_and_step(oracle_mod, inputs_mod, torch_cuda):
     note(f"      step rel err {e:.2e}, dt {dt:.6e} vs {dt_ref:.6e}")
     assert abs(dt - dt_ref) <= 1e-14 * dt_ref
     assert e < 1e-11
+
+
+def _window(O, pr, p_full, j0, j1, i0, i1, halo, flags=0, fixed_dt=0.0, alpha=(0.0, 0.0)):
+    """The sub-problem over rows [j0, j1) x columns [i0, i1) widened by `halo` nodes where it is
+    not at the domain's edge, with the same spacing and reflective walls; returns it with the slice
+    of its output region."""
+    import copy
+    ny, nx = pr.b.shape
+    ej0, ej1, ei0, ei1 = max(j0 - halo, 0), min(j1 + halo, ny), max(i0 - halo, 0), min(i1 + halo, nx)
+    sub = copy.copy(pr)
+    sl = (slice(ej0, ej1), slice(ei0, ei1))
+    sub.state = np.ascontiguousarray(pr.state[(slice(None),) + sl])
+    sub.b, sub.bx, sub.by = [np.ascontiguousarray(a[sl]) for a in (pr.b, pr.bx, pr.by)]
+    sub.nx, sub.ny = ei1 - ei0, ej1 - ej0
+    x0, _, y0, _ = pr.domain
+    dom = (x0 + ei0 * pr.dx, x0 + ei1 * pr.dx, y0 + ej0 * pr.dy, y0 + ej1 * pr.dy)
+    ps = O.params_of(sub, domain=dom, flags=flags, fixed_dt=fixed_dt, alpha_x=(alpha[0],) * 3,
+                     alpha_y=(alpha[1],) * 3)
+    inner = (slice(j0 - ej0, j1 - ej0), slice(i0 - ei0, i1 - ei0))
+    return sub, ps, sl, inner
+
+
+@pytest.mark.slow
+def test_large_grid_beyond_4gib_sampled(oracle_mod, inputs_mod, torch_cuda):
+    """A 12288 x 8192 dam break, whose 9-field state (7.2 GB) and many of whose planes lie beyond
+    4 GiB offsets: the right-hand side and one SSP-RK3 step (fixed dt and alpha, so that a window
+    can reproduce them) against the oracle on windows at a corner (a lake at rest: its right-hand
+    side is round-off), across the front in the middle and at the far corner. Each window is
+    widened by the stencil's reach (2 nodes per right-hand side and 1 per limiter, so 9 for a step)
+    and compared on its interior with the bars of the small cases: per equation group, the larger
+    of 1e-13 (right-hand side) or 1e-11 (step) of the group's magnitude and 32 times the oracle's
+    own round-off envelope on the window. An addressing fault would show as an error of order one."""
+    from paper_2208_01260_amd.solver import FIXED_ALPHA, FIXED_DT
+
+    torch, O = torch_cuda, oracle_mod
+    note("[large] generating 12288 x 8192")
+    pr = inputs_mod.c3_2d(12288, ny=8192)
+    ny, nx = pr.b.shape
+    p = O.params_of(pr)
+    ax, ay = O.alpha(p, pr.state, pr.b, pr.bx, pr.by)
+    dt = 0.5 * pr.cfl / (ax / pr.dx + ay / pr.dy)
+    wins = [(0, 64, 0, 64), (ny // 2 - 32, ny // 2 + 32, nx // 2 - 32, nx // 2 + 32), (ny - 64, ny, nx - 64, nx)]
+    with solver_for(pr, flags=FIXED_DT | FIXED_ALPHA, fixed_dt=dt, alpha=(ax, ay)) as s:
+        st = to_dev(torch, pr.state)
+        note(f"[large] state {st.numel() * 8 / 2**30:.2f} GiB; rhs")
+        r = s.rhs(st, alpha=(ax, ay))
+        torch.cuda.synchronize()
+        for (j0, j1, i0, i1) in wins:
+            sub, ps, sl, inner = _window(O, pr, p, j0, j1, i0, i1, 4)
+            full, env = envelope(lambda x: O.rhs(ps, x, sub.b, sub.bx, sub.by, ax, ay), sub.state, GROUPS2)
+            ref = full[(slice(None),) + inner]
+            got = r[:, j0:j1, i0:i1].cpu().numpy()
+            ratio = check_envelope(got, ref, env, GROUPS2)
+            note(f"      rhs window rows {j0}:{j1} cols {i0}:{i1}: rel err {rel_err(got, ref, GROUPS2):.2e} "
+                 f"err/allowed {ratio:.3f}")
+            assert ratio <= 1, (j0, i0, ratio)
+        del r
+        note("[large] step")
+        s.step(st, sync=True)
+        for (j0, j1, i0, i1) in wins:
+            sub, ps, sl, inner = _window(O, pr, p, j0, j1, i0, i1, 12, flags=O.FIXED_DT | O.FIXED_ALPHA,
+                                         fixed_dt=dt, alpha=(ax, ay))
+            full, env = envelope(lambda x: O.step(ps, x, sub.b, sub.bx, sub.by)[0], sub.state, GROUPS2)
+            ref = full[(slice(None),) + inner]
+            got = st[:, j0:j1, i0:i1].cpu().numpy()
+            worst = 0.0
+            for k, g in enumerate(GROUPS2):
+                g = list(g)
+                allowed = max(1e-11 * np.abs(ref[g]).max(), ENVELOPE_FACTOR * env[k], 1e-300)
+                worst = max(worst, np.abs(got[g] - ref[g]).max() / allowed)
+            note(f"      step window rows {j0}:{j1} cols {i0}:{i1}: rel err {rel_err(got, ref, GROUPS2):.2e} "
+                 f"err/allowed {worst:.3f}")
+            assert worst <= 1, (j0, i0, worst)
