@@ -135,159 +135,11 @@ __device__ __forceinline__ void proj_vjp(double l1a, double l3a, double i2c, dou
   utb -= v0 * yb[1];
 }
 
-// Reverse of interface_flux for the four NodeF of the stencil X[0..3] (nodes i-1 .. i+2):
-// ob = adjoints of the 14 interface quantities in IfO order (F0..2, B0..2, P0..2, PB, M0..2,
-// MB). Adds the adjoints of the NodeF fields into Xb[0..3].
-__device__ __forceinline__ void interface_vjp(const NodeF<double> X[4], double alpha, double dx, double eps, double g,
-                                              const double ob[14], NodeB Xb[4]) {
-  const NodeF<double>& XA = X[0];
-  const NodeF<double>& XB = X[1];
-  const NodeF<double>& XC = X[2];
-  const NodeF<double>& XD = X[3];
-  // ---- forward: interface state and characteristic matrices
-  const double em = 0.5 * (XB.e + XC.e), mnm = 0.5 * (XB.mn + XC.mn), mtm = 0.5 * (XB.mt + XC.mt);
-  const double bm = 0.5 * (XB.b + XC.b);
-  const double h = em - bm, ih = rcp(h);
-  const double un = mnm * ih, ut = mtm * ih;
-  const double cs = sqrt(g * h), i2c = 0.5 * rcp(cs);
-  const double l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
-  const double ha = 0.5 * alpha, hdx = 0.5 * dx, hadx = ha * dx;
-  // projected values per node: lf, lu, lp, ld
-  double lf[4][3], lu[4][3], lp[4][3], ld[4][3];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const NodeF<double>& Y = X[k];
-    lf[k][0] = l1a * Y.f0 - i2c * Y.f1; lf[k][1] = Y.f2 - ut * Y.f0; lf[k][2] = l3a * Y.f0 + i2c * Y.f1;
-    lu[k][0] = l1a * Y.e - i2c * Y.mn;  lu[k][1] = Y.mt - ut * Y.e;  lu[k][2] = l3a * Y.e + i2c * Y.mn;
-    lp[k][0] = l1a * Y.p0 - i2c * Y.p1; lp[k][1] = Y.p2 - ut * Y.p0; lp[k][2] = l3a * Y.p0 + i2c * Y.p1;
-    ld[k][0] = l1a * Y.d0 - i2c * Y.d1; ld[k][1] = Y.d2 - ut * Y.d0; ld[k][2] = l3a * Y.d0 + i2c * Y.d1;
-  }
-  // split values: fp/sp for nodes 0..2 ("+" side), fm/sm for nodes 1..3 ("-" side)
-  double fp[4][3], sp[4][3], fm[4][3], sm[4][3];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      fp[k][c] = 0.5 * lf[k][c] + ha * lu[k][c];
-      fm[k][c] = 0.5 * lf[k][c] - ha * lu[k][c];
-      sp[k][c] = hdx * lp[k][c] + hadx * ld[k][c];
-      sm[k][c] = hdx * lp[k][c] - hadx * ld[k][c];
-    }
-  const double bA = XA.b, bB = XB.b, bC = XC.b, bD = XD.b;
-  const double sbA = dx * XA.bn, sbB = dx * XB.bn, sbC = dx * XC.bn, sbD = dx * XD.bn;
-  double s[3], t[3], Z[3], wp[3][3], wm[3][3];
-  const double i4dx = 0.25 / dx, i12dx = K112 / dx;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double vp = side_value(fp[0][k], fp[1][k], fp[2][k], sp[0][k], sp[1][k], sp[2][k], eps, wp[k]);
-    const double vm = side_value(fm[3][k], fm[2][k], fm[1][k], -sm[3][k], -sm[2][k], -sm[1][k], eps, wm[k]);
-    s[k] = vp + vm;
-    Z[k] = with_value(bA, bB, bC, sbA, sbB, sbC, wp[k]) + with_value(bD, bC, bB, -sbD, -sbC, -sbB, wm[k]);
-    t[k] = ((fp[0][k] - fm[3][k]) + 8.0 * (fm[2][k] - fp[1][k]) + 7.0 * (fp[2][k] - fm[1][k])) * i4dx +
-           ((sp[0][k] + sm[3][k]) - 2.0 * (sp[1][k] + sm[2][k]) - 5.0 * (sp[2][k] + sm[1][k])) * i12dx;
-  }
-  const double umc = un - cs, upc = un + cs;
-  const double sb1 = -0.5 * i2c * Z[0], sb3 = 0.5 * i2c * Z[2];
-
-  // ---- reverse: outputs to s, t, Z and the frame quantities
-  double unb = 0.0, utb = 0.0, csb = 0.0, i2cb = 0.0, l1ab = 0.0, l3ab = 0.0;
-  double umcb = 0.0, upcb = 0.0;
-  double sbar[3], tbar[3], Zb[3];
-  sbar[0] = ob[0] + umc * ob[1] + ut * ob[2];
-  sbar[2] = ob[0] + upc * ob[1] + ut * ob[2];
-  sbar[1] = ob[2];
-  umcb += s[0] * ob[1]; upcb += s[2] * ob[1]; utb += (s[0] + s[2]) * ob[2];
-  const double sb1b = ob[3] + umc * ob[4] + ut * ob[5];
-  const double sb3b = ob[3] + upc * ob[4] + ut * ob[5];
-  umcb += sb1 * ob[4]; upcb += sb3 * ob[4]; utb += (sb1 + sb3) * ob[5];
-  Zb[0] = -0.5 * i2c * sb1b; Zb[2] = 0.5 * i2c * sb3b; Zb[1] = 0.0;
-  i2cb += -0.5 * Z[0] * sb1b + 0.5 * Z[2] * sb3b;
-  tbar[0] = ob[6] + umc * ob[7] + ut * ob[8];
-  tbar[2] = ob[6] + upc * ob[7] + ut * ob[8];
-  tbar[1] = ob[8];
-  umcb += t[0] * ob[7]; upcb += t[2] * ob[7]; utb += (t[0] + t[2]) * ob[8];
-  unb += umcb + upcb;
-  csb += upcb - umcb;
-  // PB = 1/2 (((bA - bD) + 15 (bC - bB)) i4dx + ((sbA + sbD) - 7 (sbB + sbC)) i12dx)
-  double bAb = 0.5 * i4dx * ob[9], bDb = -0.5 * i4dx * ob[9];
-  double bCb = 7.5 * i4dx * ob[9], bBb = -7.5 * i4dx * ob[9];
-  double sbAb = 0.5 * i12dx * ob[9], sbDb = 0.5 * i12dx * ob[9];
-  double sbBb = -3.5 * i12dx * ob[9], sbCb = -3.5 * i12dx * ob[9];
-  // mixed: M_j = (7 (q_B + q_C) - (q_A + q_D)) / 12
-  {
-    const double m7[4] = {7.0 * K112 * ob[10], 7.0 * K112 * ob[11], 7.0 * K112 * ob[12], 7.0 * K112 * ob[13]};
-    const double m1[4] = {K112 * ob[10], K112 * ob[11], K112 * ob[12], K112 * ob[13]};
-    Xb[1].q0 += m7[0]; Xb[1].q1 += m7[1]; Xb[1].q2 += m7[2]; Xb[1].bt += m7[3];
-    Xb[2].q0 += m7[0]; Xb[2].q1 += m7[1]; Xb[2].q2 += m7[2]; Xb[2].bt += m7[3];
-    Xb[0].q0 -= m1[0]; Xb[0].q1 -= m1[1]; Xb[0].q2 -= m1[2]; Xb[0].bt -= m1[3];
-    Xb[3].q0 -= m1[0]; Xb[3].q1 -= m1[1]; Xb[3].q2 -= m1[2]; Xb[3].bt -= m1[3];
-  }
-  // per characteristic field: reverse of t, s (HWENO both sides) and Z (bottom reuse)
-  double fpb[4][3], spb[4][3], fmb[4][3], smb[4][3];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fpb[k][c] = spb[k][c] = fmb[k][c] = smb[k][c] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double tb = tbar[k];
-    fpb[0][k] += i4dx * tb; fmb[3][k] -= i4dx * tb;
-    fmb[2][k] += 8.0 * i4dx * tb; fpb[1][k] -= 8.0 * i4dx * tb;
-    fpb[2][k] += 7.0 * i4dx * tb; fmb[1][k] -= 7.0 * i4dx * tb;
-    spb[0][k] += i12dx * tb; smb[3][k] += i12dx * tb;
-    spb[1][k] -= 2.0 * i12dx * tb; smb[2][k] -= 2.0 * i12dx * tb;
-    spb[2][k] -= 5.0 * i12dx * tb; smb[1][k] -= 5.0 * i12dx * tb;
-    // bottom reuse: Z = HW+(b, sb; wp) + HW-(b mirrored, -sb; wm)
-    double wpb[3] = {0.0, 0.0, 0.0}, wmb[3] = {0.0, 0.0, 0.0};
-    if (k != 1) {
-      double nsDb = 0.0, nsCb = 0.0, nsBb = 0.0;
-      hweno_with_vjp(bA, bB, bC, sbA, sbB, sbC, wp[k], Zb[k], bAb, bBb, bCb, sbAb, sbBb, sbCb, wpb);
-      hweno_with_vjp(bD, bC, bB, -sbD, -sbC, -sbB, wm[k], Zb[k], bDb, bCb, bBb, nsDb, nsCb, nsBb, wmb);
-      sbDb -= nsDb; sbCb -= nsCb; sbBb -= nsBb;
-    }
-    // "+" side: HS(fp0, fp1, fp2; sp0, sp1, sp2)
-    hweno_side_vjp(fp[0][k], fp[1][k], fp[2][k], sp[0][k], sp[1][k], sp[2][k], eps, sbar[k], wpb, fpb[0][k],
-                   fpb[1][k], fpb[2][k], spb[0][k], spb[1][k], spb[2][k]);
-    // "-" side: HS(fm3, fm2, fm1; -sm3, -sm2, -sm1)
-    double n3 = 0.0, n2 = 0.0, n1 = 0.0;
-    hweno_side_vjp(fm[3][k], fm[2][k], fm[1][k], -sm[3][k], -sm[2][k], -sm[1][k], eps, sbar[k], wmb, fmb[3][k],
-                   fmb[2][k], fmb[1][k], n3, n2, n1);
-    smb[3][k] -= n3; smb[2][k] -= n2; smb[1][k] -= n1;
-  }
-  // split values -> projected values -> node fields and the matrices
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    double lfb[3], lub[3], lpb[3], ldb[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      lfb[c] = 0.5 * (fpb[k][c] + fmb[k][c]);
-      lub[c] = ha * (fpb[k][c] - fmb[k][c]);
-      lpb[c] = hdx * (spb[k][c] + smb[k][c]);
-      ldb[c] = hadx * (spb[k][c] - smb[k][c]);
-    }
-    const NodeF<double>& Y = X[k];
-    NodeB& B = Xb[k];
-    proj_vjp(l1a, l3a, i2c, ut, Y.f0, Y.f1, lfb, B.f0, B.f1, B.f2, l1ab, l3ab, i2cb, utb);
-    proj_vjp(l1a, l3a, i2c, ut, Y.e, Y.mn, lub, B.e, B.mn, B.mt, l1ab, l3ab, i2cb, utb);
-    proj_vjp(l1a, l3a, i2c, ut, Y.p0, Y.p1, lpb, B.p0, B.p1, B.p2, l1ab, l3ab, i2cb, utb);
-    proj_vjp(l1a, l3a, i2c, ut, Y.d0, Y.d1, ldb, B.d0, B.d1, B.d2, l1ab, l3ab, i2cb, utb);
-  }
-  Xb[0].b += bAb; Xb[1].b += bBb; Xb[2].b += bCb; Xb[3].b += bDb;
-  Xb[0].bn += dx * sbAb; Xb[1].bn += dx * sbBb; Xb[2].bn += dx * sbCb; Xb[3].bn += dx * sbDb;
-  // matrices -> interface state
-  unb += i2c * (l1ab - l3ab);
-  csb += i2c * (l1ab + l3ab);
-  i2cb += (un + cs) * l1ab + (cs - un) * l3ab;
-  csb += -2.0 * i2c * i2c * i2cb;       // i2c = 1 / (2 cs)
-  double hb = g * i2c * csb;            // cs = sqrt(g h)
-  const double mnmb = ih * unb, mtmb = ih * utb;
-  const double ihb = mnm * unb + mtm * utb;
-  hb -= ih * ih * ihb;
-  const double emb = hb, bmb = -hb;
-  Xb[1].e += 0.5 * emb; Xb[2].e += 0.5 * emb;
-  Xb[1].mn += 0.5 * mnmb; Xb[2].mn += 0.5 * mnmb;
-  Xb[1].mt += 0.5 * mtmb; Xb[2].mt += 0.5 * mtmb;
-  Xb[1].b += 0.5 * bmb; Xb[2].b += 0.5 * bmb;
+// Row f of the characteristic matrix L applied to a triple: rows (l1a, -i2c, 0), (-ut, 0, 1),
+// (l3a, i2c, 0); proj_vjp is its reverse over the three rows.
+__device__ __forceinline__ double proj_row(int f, double l1a, double l3a, double i2c, double ut, double v0, double v1,
+                                           double v2) {
+  return f == 0 ? l1a * v0 - i2c * v1 : (f == 1 ? v2 - ut * v0 : l3a * v0 + i2c * v1);
 }
 
 // Reverse of node_frame<DIR>: adds the adjoint of the raw record r (slots of hweno_device.hpp)
