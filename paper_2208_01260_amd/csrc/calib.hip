@@ -8,7 +8,7 @@
 #include <cstring>
 #include <vector>
 
-namespace {
+namespace swe_calib {
 
 constexpr int CHAINS = 4;   // independent FMA chains per lane
 constexpr int UNROLL = 16;  // FMAs per chain per loop trip
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64) void k_fma_stream(double* out, unsigned long lo
   }
 }
 
-}  // namespace
+}  // namespace swe_calib
 
 extern "C" {
 
@@ -84,12 +84,12 @@ int swe_calib_fp64_fma(int waves_per_simd, double seconds, double* tflops, doubl
   int rc = 0;
   std::vector<double> rate, mhz;
   std::vector<unsigned long long> h(2 * (size_t)nblk);
-  const double flops = 2.0 * CHAINS * UNROLL * (double)iters * 64.0 * nblk;
+  const double flops = 2.0 * swe_calib::CHAINS * swe_calib::UNROLL * (double)iters * 64.0 * nblk;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = -3;
   const auto t0 = std::chrono::steady_clock::now();
   while (rc == 0) {
     if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = -3; break; }
-    hipLaunchKernelGGL(k_fma_stream, dim3(nblk), dim3(64), lds, 0, out, spans, iters, 0.999999, 1e-7);
+    hipLaunchKernelGGL(swe_calib::k_fma_stream, dim3(nblk), dim3(64), lds, 0, out, spans, iters, 0.999999, 1e-7);
     if (hipGetLastError() != hipSuccess || hipEventRecord(e1, nullptr) != hipSuccess ||
         hipEventSynchronize(e1) != hipSuccess) { rc = -3; break; }
     float ms = 0.f;
