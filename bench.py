@@ -255,8 +255,8 @@ def main():
                     help="also run a plain device copy of this many MiB (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
-              "the domain decomposition it would use is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; the solver has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "each extra GPU would take a slab of rows with a two-row halo exchange per stage", file=sys.stderr)
         sys.exit(2)
 
     import torch
