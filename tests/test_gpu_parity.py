@@ -369,3 +369,39 @@ def test_large_grid_beyond_4gib_sampled(oracle_mod, inputs_mod, torch_cuda):
             note(f"      step window rows {j0}:{j1} cols {i0}:{i1}: rel err {rel_err(got, ref, GROUPS2):.2e} "
                  f"err/allowed {worst:.3f}")
             assert worst <= 1, (j0, i0, worst)
+
+
+def test_thin_and_tile_edge_grids(oracle_mod, inputs_mod, torch_cuda):
+    """Extreme aspect ratios and tile-edge widths against the oracle, reflective and periodic:
+    4 or 5 rows (a march shorter than its start-up), 4 columns (one tile with 60 idle lanes),
+    and widths that are exact multiples of the 60-column tile. Same bars as the small cases."""
+    import copy
+
+    torch, O = torch_cuda, oracle_mod
+    fails = []
+    for nx, ny in ((300, 4), (4, 300), (120, 5), (5, 121), (60, 60), (180, 7)):
+        base = inputs_mod.c2_2d(nx, "smooth", ny=ny)
+        for bcname, bc in (("refl", (1, 1)), ("per", (0, 0))):
+            pr = copy.copy(base)
+            pr.bc = bc
+            p = O.params_of(pr)
+            with solver_for(pr) as s:
+                st = to_dev(torch, pr.state)
+                r = s.rhs(st).cpu().numpy()
+                dt = s.step(st, sync=True)
+                got = st.cpu().numpy()
+            ref, env = envelope(lambda x: O.rhs(p, x, pr.b, pr.bx, pr.by), pr.state, GROUPS2)
+            ratio = check_envelope(r, ref, env, GROUPS2)
+            sref, dt_ref = O.step(p, pr.state, pr.b, pr.bx, pr.by)
+            fixed = O.params_of(pr, flags=O.FIXED_DT, fixed_dt=dt_ref)
+            _, senv = envelope(lambda x: O.step(fixed, x, pr.b, pr.bx, pr.by)[0], pr.state, GROUPS2)
+            worst = 0.0
+            for k, g in enumerate(GROUPS2):
+                g = list(g)
+                allowed = max(1e-11 * np.abs(sref[g]).max(), ENVELOPE_FACTOR * senv[k], 1e-300)
+                worst = max(worst, np.abs(got[g] - sref[g]).max() / allowed)
+            note(f"[thin] {nx}x{ny} {bcname}: rhs err/allowed {ratio:.3f}, step err/allowed {worst:.3f}, "
+                 f"dt {dt:.6e} vs {dt_ref:.6e}")
+            if not (ratio <= 1 and worst <= 1 and abs(dt - dt_ref) <= 1e-14 * dt_ref):
+                fails.append((nx, ny, bcname, ratio, worst))
+    assert not fails, fails
