@@ -93,6 +93,8 @@ def flop_counts():
 
 def cpu_baseline(pr, steps):
     """The oracle on this host: `steps` SSP-RK3 steps of the same workload state."""
+    import numpy as np
+
     import oracle
 
     oracle.build()
@@ -104,10 +106,28 @@ def cpu_baseline(pr, steps):
     for _ in range(steps):
         state, _dt = oracle.step(p, state, pr.b, pr.bx, pr.by)
     dt = time.perf_counter() - t0
-    return {"value": 3.0 * pr.cells * steps / dt, "unit": "cell-RHS/s", "cores": oracle.get_threads(),
+    used = oracle.get_threads()
+    # the same step on one thread, on a 1024 x 1024 window of the state (reflective walls at its edges)
+    import copy
+    w = min(1024, pr.nx, pr.ny)
+    sub = copy.copy(pr)
+    sl = (slice(0, w), slice(0, w))
+    sub.state = np.ascontiguousarray(pr.state[(slice(None),) + sl])
+    sub.b, sub.bx, sub.by = [np.ascontiguousarray(a[sl]) for a in (pr.b, pr.bx, pr.by)]
+    sub.nx = sub.ny = w
+    x0, _, y0, _ = pr.domain
+    ps = oracle.params_of(sub, domain=(x0, x0 + w * pr.dx, y0, y0 + w * pr.dy))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.step(ps, sub.state, sub.b, sub.bx, sub.by)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    return {"value": 3.0 * pr.cells * steps / dt, "unit": "cell-RHS/s", "cores": used,
             "kind": "oracle",
             "sample": f"{steps} SSP-RK3 step(s) (3 right-hand sides, limiter, update each) of the same "
-                      f"{pr.nx}x{pr.ny} dam-break state, {dt:.1f} s wall on {oracle.get_threads()} threads"}
+                      f"{pr.nx}x{pr.ny} dam-break state, {dt:.1f} s wall on {used} threads",
+            "single_thread_value": 3.0 * w * w / dt1,
+            "single_thread_sample": f"1 step of a {w}x{w} window of the same state on 1 thread, {dt1:.1f} s wall"}
 
 
 def single_precision(args, torch, pr, f_rhs):
