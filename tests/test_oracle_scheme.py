@@ -56,16 +56,18 @@ def test_lake_at_rest_2d_matches_table_3(oracle_mod, inputs_mod):
 
 
 def random_lake(I, dim, n, bc, step_bottom=False):
-    """Lake at rest (eta = const, m = w = 0, all derivatives of U zero) over a random bottom."""
+    """Lake at rest (eta = const, m = w = 0, all derivatives of U zero) over a random bottom, drawn
+    from a generator seeded by the case itself so that it does not depend on the test order."""
+    rng = np.random.default_rng([2208, dim, n, bc, int(step_bottom)])
     if dim == 1:
         x = I.nodes_1d(n, 0.0, 1.0)
-        b = 0.5 * np.sin(2 * np.pi * x + RNG.uniform(0, 6)) + 0.3 * np.exp(-((x - 0.4) / 0.1) ** 2)
-        bx = RNG.normal(size=n)  # the balance holds for any B
+        b = 0.5 * np.sin(2 * np.pi * x + rng.uniform(0, 6)) + 0.3 * np.exp(-((x - 0.4) / 0.1) ** 2)
+        bx = rng.normal(size=n)  # the balance holds for any B
         if step_bottom:
             b = np.where((x > 0.3) & (x < 0.6), 0.8, 0.0)
             bx = np.zeros(n)
         st = np.zeros((4, n))
-        st[0] = 2.0 + RNG.uniform(0, 1)
+        st[0] = 2.0 + rng.uniform(0, 1)
         return I.Problem("lake", 1, n, 1, (0.0, 1.0, 0.0, 1.0), (bc, 0), st, b, bx, None)
     X, Y = I.nodes_2d(n, n + 3, (0.0, 1.0, 0.0, 1.2))
     b = 0.6 * np.exp(-((X - 0.5) ** 2 + (Y - 0.6) ** 2) / 0.02) + 0.2 * np.sin(3 * X) * np.cos(2 * Y)
@@ -73,8 +75,8 @@ def random_lake(I, dim, n, bc, step_bottom=False):
         b = np.where(X + Y > 1.0, 0.7, 0.1)
     st = np.zeros((9,) + X.shape)
     st[0] = 1.5
-    return I.Problem("lake", 2, n, n + 3, (0.0, 1.0, 0.0, 1.2), (bc, bc), st, b, RNG.normal(size=X.shape),
-                     RNG.normal(size=X.shape))
+    return I.Problem("lake", 2, n, n + 3, (0.0, 1.0, 0.0, 1.2), (bc, bc), st, b, rng.normal(size=X.shape),
+                     rng.normal(size=X.shape))
 
 
 @pytest.mark.parametrize("dim", [1, 2])
@@ -88,8 +90,11 @@ def test_rhs_and_limiter_vanish_at_rest(oracle_mod, inputs_mod, dim, bc, step_bo
     for eps in (1e-6, 1e-10):
         p = O.params_of(pr, eps=eps)
         r = O.rhs(p, pr.state, pr.b, pr.bx, pr.by, 7.3, 5.1)
-        scale = 9.812 * pr.state[0].max() * (np.abs(pr.b).max() + np.abs(pr.bx).max()) / min(pr.dx, pr.dy)
-        assert np.abs(r).max() <= 1e-14 * scale, np.abs(r).max() / scale
+        # zero in exact arithmetic; the round-off bar is 256 units of 2^-53 of the flux magnitude
+        # g eta (eta / 2 + |b| + |B|) / dx (the worst of 960 random lakes of this recipe is 132)
+        e = pr.state[0].max()
+        scale = 9.812 * e * (0.5 * e + np.abs(pr.b).max() + np.abs(pr.bx).max()) / min(pr.dx, pr.dy)
+        assert np.abs(r).max() <= 256 * 2.0**-53 * scale, np.abs(r).max() / scale
         dm = O.limit(p, pr.state, pr.b, pr.bx, pr.by)
         assert np.all(dm == 0.0)
 
