@@ -71,7 +71,7 @@ typedef struct {
   double x0, x1, y0, y1;    /* domain; x1 > x0 (and y1 > y0 in 2D) */
   double g;                 /* gravitational constant, > 0 (the paper uses 9.812, Sec. 4) */
   double cfl;               /* CFL number, > 0 (the paper uses 0.6, Sec. 4) */
-  double eps;               /* epsilon of the nonlinear weights, > 0 (1e-6, eq. (2.7)) */
+  double eps;               /* epsilon of the nonlinear weights, >= 1e-20 (1e-6, eq. (2.7)) */
   int bc_x, bc_y;           /* SWE_BC_PERIODIC or SWE_BC_REFLECTIVE (mirror about the wall face) */
   int flags;                /* SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER */
   double fixed_dt;          /* > 0 when SWE_FIXED_DT is set */

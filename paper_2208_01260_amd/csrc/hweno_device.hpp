@@ -98,27 +98,34 @@ __device__ __forceinline__ void node_frame(const T* __restrict__ r, T g, NodeF<T
   o.b = b; o.bn = bn; o.bt = bt;
 }
 
-// Weights of one side up to a common factor (u_l) and the reciprocal of their sum.
+// Weights of one side up to a common factor (u_l) and their sum.
 template <class T>
-struct W3 { T u1, u2, u3, is; };
+struct W3 { T u1, u2, u3, su; };
 
 // Upwind HWENO value at x_{i+1/2} from the stencil (i-1, i, i+1): f are split flux values,
-// s = dx * (split derivative-flux values). Smoothness indicators and candidate values of
-// Sec. 2.1. Each indicator is s1^2 + (k_a a)^2 + (k_c c)^2 with the square roots k of its
-// coefficients folded into the differences a, c (and eps added to the shared s1^2). The weights
-// gamma_l / (beta_l + eps)^2 are kept unnormalised as gamma_1 e2 e3 : gamma_2 e1 e3 : gamma_3 e1 e2
-// (e_l = (beta_l + eps)^2, scaled by 10/3); the candidates are formed doubled, and the value is
-// divided once by twice the weights' sum.
+// s = dx * (split derivative-flux values); candidate values and smoothness indicators of
+// Sec. 2.1. The value is returned as f1 + N / (2 su): each doubled candidate 2 q_l is written as
+// 2 f1 + r_l with the deviations
+//   r1 = (f0 - f1) + (s0 + 5 s1) / 3,  r2 = (f2 - f1) + (s1 - s2) / 3,  r3 = (f0 - 2 f1 + f2) / 6 + s1,
+// so N = sum_l u_l r_l. Each indicator is s1^2 + (k_a a)^2 + (k_c c)^2 with the square roots k of
+// its coefficients folded into the differences a, c (eps is added once to the shared s1^2); the
+// first differences are taken from the deviations, 3 d01 + s0 + 2 s1 = 3 (r1 - s1) and
+// 3 d12 + s2 + 2 s1 = 3 (s1 - r2). The weights gamma_l / (beta_l + eps)^2 are kept unnormalised as
+// gamma_1 e2 e3 : gamma_2 e1 e3 : gamma_3 e1 e2 (e_l = (beta_l + eps)^2, scaled by 10/3). Returns N;
+// w receives the weights and their sum su.
 template <class T>
 __device__ __forceinline__ T hweno_side(T f0, T f1, T f2, T s0, T s1, T s2, T eps, W3<T>& w) {
-  const T d01 = f0 - f1, d12 = f1 - f2;
+  const T d01 = f0 - f1, d12 = f1 - f2, dd = d01 - d12;
+  const T r1 = fma(T(1.0 / 3.0), fma(T(5.0), s1, s0), d01);
+  const T r2 = fma(T(1.0 / 3.0), s1 - s2, -d12);
+  const T r3 = fma(T(1.0 / 6.0), dd, s1);
   const T te = fma(s1, s1, eps);
-  const T ra = T(2.0 * RA) * s1, rc = T(RC) * s1;
-  const T a1 = fma(T(3.0 * RA), d01, fma(T(RA), s0, ra));  // RA (3 d01 + s0 + 2 s1)
+  const T ma = T(3.0 * RA) * s1, rc = T(RC) * s1;
+  const T a1 = fma(T(3.0 * RA), r1, -ma);                   // RA (3 d01 + s0 + 2 s1)
   const T c1 = fma(T(2.0 * RC), d01, fma(T(RC), s0, rc));  // RC (2 d01 + s0 + s1)
-  const T a2 = fma(T(3.0 * RA), d12, fma(T(RA), s2, ra));  // RA (3 d12 + s2 + 2 s1)
+  const T a2 = fma(T(-3.0 * RA), r2, ma);                   // RA (3 d12 + s2 + 2 s1)
   const T c2 = fma(T(2.0 * RC), d12, fma(T(RC), s2, rc));  // RC (2 d12 + s2 + s1)
-  const T a3 = T(RB) * (d01 - d12);                         // RB (f0 - 2 f1 + f2)
+  const T a3 = T(RB) * dd;                                  // RB (f0 - 2 f1 + f2)
   const T c3 = fma(T(RD), d01 + d12, T(2.0 * RD) * s1);     // RD (f0 - f2 + 2 s1)
   const T g1 = fma(a1, a1, fma(c1, c1, te));
   const T g2 = fma(a2, a2, fma(c2, c2, te));
@@ -127,23 +134,42 @@ __device__ __forceinline__ T hweno_side(T f0, T f1, T f2, T s0, T s1, T s2, T ep
   w.u1 = e2 * e3;
   w.u2 = e1 * e3;
   w.u3 = T(4.0 / 3.0) * (e1 * e2);
-  const T su = (w.u1 + w.u2) + w.u3;
-  w.is = rcp(su + su);
-  // doubled candidates: 2 q_l
-  const T q1 = fma(T(1.0 / 3.0), fma(T(5.0), s1, s0), f0 + f1);
-  const T q2 = fma(T(1.0 / 3.0), s1 - s2, f1 + f2);
-  const T q3 = fma(T(1.0 / 6.0), fma(T(10.0), f1, f0 + f2), s1);
-  return ((w.u1 * q1 + w.u2 * q2) + w.u3 * q3) * w.is;
+  w.su = (w.u1 + w.u2) + w.u3;
+  return fma(w.u3, r3, fma(w.u2, r2, w.u1 * r1));
 }
 
-// The three candidate values combined with given weights (the source split of Step 2).
+// The deviations of the three candidates combined with given weights (the source split of
+// Step 2): returns N for the value f1 + N / (2 su).
 template <class T>
 __device__ __forceinline__ T hweno_with(T f0, T f1, T f2, T s0, T s1, T s2, const W3<T>& w) {
-  const T q1 = fma(T(1.0 / 3.0), fma(T(5.0), s1, s0), f0 + f1);
-  const T q2 = fma(T(1.0 / 3.0), s1 - s2, f1 + f2);
-  const T q3 = fma(T(1.0 / 6.0), fma(T(10.0), f1, f0 + f2), s1);
-  return ((w.u1 * q1 + w.u2 * q2) + w.u3 * q3) * w.is;
+  const T d01 = f0 - f1, d12 = f1 - f2;
+  const T r1 = fma(T(1.0 / 3.0), fma(T(5.0), s1, s0), d01);
+  const T r2 = fma(T(1.0 / 3.0), s1 - s2, -d12);
+  const T r3 = fma(T(1.0 / 6.0), d01 - d12, s1);
+  return fma(w.u3, r3, fma(w.u2, r2, w.u1 * r1));
 }
+
+// Sum of the two sides' values at one interface, (fa + Na / (2 sa)) + (fb + Nb / (2 sb)). In
+// double precision both share one reciprocal of 2 sa sb (the sums lie between 3 eps^4 and about
+// 1e150 for any physical state, so the product stays normal); in single precision, where the
+// product of two sums near 3 eps^4 would underflow, each side has its own.
+template <class T>
+struct Pair {
+  T q, sa, sb;  // q = 1 / (2 sa sb) (double) or the pair (1 / (2 sa), 1 / (2 sb)) (float)
+  __device__ __forceinline__ Pair(T sa_, T sb_) : sa(sa_), sb(sb_) {
+    if constexpr (sizeof(T) == 8) {
+      const T p = sa * sb;
+      q = rcp(p + p);
+    } else {
+      q = rcp(sa + sa);
+      sb = rcp(sb + sb);
+    }
+  }
+  __device__ __forceinline__ T sum(T fa, T na, T fb, T nb) const {
+    if constexpr (sizeof(T) == 8) return fma(fma(na, sb, nb * sa), q, fa + fb);
+    else return fma(na, q, fa) + fma(nb, sb, fb);
+  }
+};
 
 // Interface quantities at x_{i+1/2}, frame order (eta, n, t).
 template <class T>
@@ -228,11 +254,13 @@ __device__ __forceinline__ void interface_flux(Fetch fetch, T alpha, T dx, T eps
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     W3<T> wp, wm;
-    const T vp = hweno_side(fpA[k], fpB[k], fpC[k], spA[k], spB[k], spC[k], eps, wp);
-    const T vm = hweno_side(fmD[k], fmC[k], fmB[k], -smD[k], -smC[k], -smB[k], eps, wm);
-    s[k] = vp + vm;
+    const T np = hweno_side(fpA[k], fpB[k], fpC[k], spA[k], spB[k], spC[k], eps, wp);
+    const T nm = hweno_side(fmD[k], fmC[k], fmB[k], -smD[k], -smC[k], -smB[k], eps, wm);
+    const Pair<T> pr(wp.su, wm.su);
+    s[k] = pr.sum(fpB[k], np, fmC[k], nm);
     if (k != 1) {  // the middle characteristic row annihilates (0, b, 0)
-      const T z = hweno_with(bA, bB, bC, sbA, sbB, sbC, wp) + hweno_with(bD, bC, bB, -sbD, -sbC, -sbB, wm);
+      const T z = pr.sum(bB, hweno_with(bA, bB, bC, sbA, sbB, sbC, wp), bC,
+                         hweno_with(bD, bC, bB, -sbD, -sbC, -sbB, wm));
       if (k == 0) Z1 = z; else Z3 = z;
     }
     // linear Hermite derivative Q'^+(f^+, s^+/dx) + Q'^-(f^-, s^-/dx) of this characteristic field
@@ -263,26 +291,36 @@ __device__ __forceinline__ void interface_flux(Fetch fetch, T alpha, T dx, T eps
 }
 
 // HWENO limiter of one characteristic component (Sec. 2.2): mu at x_{i-1}, x_i, x_{i+1}, nu at
-// x_{i-1}, x_{i+1}; linear weights (1/4, 1/4, 1/2).
+// x_{i-1}, x_{i+1}; linear weights (1/4, 1/4, 1/2). The limited derivative is n / s / dx with the
+// weights kept unnormalised (common factor 4 / (e1 e2 e3)); the first differences of the three
+// candidates are shared with their second ones (a_l = c_l + d for the two one-sided ones).
 template <class T>
-__device__ __forceinline__ T limit_char(T mm, T m0, T mp, T nm, T np, T dx,
-                                             T idx, T eps) {
-  const T a1 = T(2.0) * (m0 - mm) - nm * dx;       // dx * p1'(x_i)
-  const T a2 = T(2.0) * (mp - m0) - np * dx;       // dx * p2'(x_i)
-  const T a3 = T(0.5) * (mp - mm);                 // dx * p3'(x_i)
-  const T c1 = (m0 - mm) - nm * dx, c2 = (mp - m0) - np * dx, c3 = (mm + mp) - T(2.0) * m0;
+struct LimNS { T n, s; };
+template <class T>
+__device__ __forceinline__ LimNS<T> limit_char_ns(T mm, T m0, T mp, T nm, T np, T dx, T eps) {
+  const T dl = m0 - mm, dr = mp - m0;
+  const T c1 = fma(-nm, dx, dl), c2 = fma(-np, dx, dr), c3 = dr - dl;
+  const T a1 = c1 + dl;                  // dx * p1'(x_i) = 2 (m0 - mm) - dx nm
+  const T a2 = c2 + dr;                  // dx * p2'(x_i) = 2 (mp - m0) - dx np
+  const T a3 = T(0.5) * (dl + dr);       // dx * p3'(x_i)
   const T g1 = fma(a1, a1, fma(T(K133) * c1, c1, eps));
   const T g2 = fma(a2, a2, fma(T(K133) * c2, c2, eps));
   const T g3 = fma(a3, a3, fma(T(K1312) * c3, c3, eps));
   const T e1 = g1 * g1, e2 = g2 * g2, e3 = g3 * g3;
-  // weights (1/4, 1/4, 1/2) / e_l up to the common factor 4 / (e1 e2 e3)
   const T u1 = e2 * e3, u2 = e1 * e3, u3 = T(2.0) * (e1 * e2);
-  const T is = rcp((u1 + u2) + u3);
-  return ((u1 * a1 + u2 * a2) + u3 * a3) * is * idx;
+  return {fma(u3, a3, fma(u2, a2, u1 * a1)), (u1 + u2) + u3};
+}
+template <class T>
+__device__ __forceinline__ T limit_char(T mm, T m0, T mp, T nm, T np, T dx, T idx, T eps) {
+  const LimNS<T> r = limit_char_ns(mm, m0, mp, nm, np, dx, eps);
+  return r.n * rcp(r.s) * idx;
 }
 
 // Limited derivative at a node in the frame of one direction: own state (e, mn, mt, b);
 // neighbour surface/momenta at -1 and +1; neighbour derivatives along this direction at -1, +1.
+// In double precision the three components share one reciprocal of the product of their weight
+// sums (each between 4 eps^4 and about 1e100 for any physical state, so the product stays
+// normal for eps >= 1e-20); in single precision each has its own.
 template <class T>
 __device__ __forceinline__ void limit_frame(T e0, T mn0, T mt0, T b0, T em, T mnm,
                                             T mtm, T ep, T mnp, T mtp, T dm0, T dm1,
@@ -292,11 +330,23 @@ __device__ __forceinline__ void limit_frame(T e0, T mn0, T mt0, T b0, T em, T mn
   const T un = mn0 * ih, ut = mt0 * ih;
   const T cs = sqrt_pos(g * h), i2c = T(0.5) * rcp(cs);
   const T l1a = (un + cs) * i2c, l3a = (cs - un) * i2c;
-  const T v1 = limit_char(l1a * em - i2c * mnm, l1a * e0 - i2c * mn0, l1a * ep - i2c * mnp,
-                               l1a * dm0 - i2c * dm1, l1a * dp0 - i2c * dp1, dx, idx, eps);
-  const T v2 = limit_char(mtm - ut * em, mt0 - ut * e0, mtp - ut * ep, dm2 - ut * dm0, dp2 - ut * dp0, dx, idx, eps);
-  const T v3 = limit_char(l3a * em + i2c * mnm, l3a * e0 + i2c * mn0, l3a * ep + i2c * mnp,
-                               l3a * dm0 + i2c * dm1, l3a * dp0 + i2c * dp1, dx, idx, eps);
+  const LimNS<T> c1 = limit_char_ns(l1a * em - i2c * mnm, l1a * e0 - i2c * mn0, l1a * ep - i2c * mnp,
+                                    l1a * dm0 - i2c * dm1, l1a * dp0 - i2c * dp1, dx, eps);
+  const LimNS<T> c2 = limit_char_ns(mtm - ut * em, mt0 - ut * e0, mtp - ut * ep, dm2 - ut * dm0, dp2 - ut * dp0, dx, eps);
+  const LimNS<T> c3 = limit_char_ns(l3a * em + i2c * mnm, l3a * e0 + i2c * mn0, l3a * ep + i2c * mnp,
+                                    l3a * dm0 + i2c * dm1, l3a * dp0 + i2c * dp1, dx, eps);
+  T v1, v2, v3;
+  if constexpr (sizeof(T) == 8) {
+    const T s13 = c1.s * c3.s;
+    const T r = rcp(s13 * c2.s) * idx;
+    v1 = (c1.n * (c2.s * c3.s)) * r;
+    v2 = (c2.n * s13) * r;
+    v3 = (c3.n * (c1.s * c2.s)) * r;
+  } else {
+    v1 = c1.n * rcp(c1.s) * idx;
+    v2 = c2.n * rcp(c2.s) * idx;
+    v3 = c3.n * rcp(c3.s) * idx;
+  }
   out[0] = v1 + v3;
   out[1] = (un - cs) * v1 + (un + cs) * v3;
   out[2] = ut * (v1 + v3) + v2;

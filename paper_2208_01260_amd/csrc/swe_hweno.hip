@@ -538,7 +538,9 @@ bool params_ok(const swe_hweno_params* p) {
   if (p->dim == 1 && p->ny != 1) return false;
   if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 31)) return false;
   if (!(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0))) return false;
-  if (!(p->g > 0) || !(p->cfl > 0) || !(p->eps > 0)) return false;
+  // eps >= 1e-20: the kernels form products of two or three weight sums, each at least of
+  // order eps^4, and these stay normal doubles down to that floor
+  if (!(p->g > 0) || !(p->cfl > 0) || !(p->eps >= 1e-20)) return false;
   if (!std::isfinite(p->g) || !std::isfinite(p->cfl) || !std::isfinite(p->eps)) return false;
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return false;
   if (p->flags & ~(SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER)) return false;

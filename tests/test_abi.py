@@ -58,7 +58,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(dim=3), dict(nx=3), dict(ny=2), dict(dim=1, ny=4), dict(x1=0.0), dict(y1=-1.0), dict(g=0.0),
-    dict(cfl=-1.0), dict(eps=0.0), dict(bc_x=2), dict(flags=64), dict(flags=1, fixed_dt=0.0),
+    dict(cfl=-1.0), dict(eps=0.0), dict(eps=1e-21), dict(bc_x=2), dict(flags=64), dict(flags=1, fixed_dt=0.0),
     dict(flags=2, alpha_x=1.0, alpha_y=0.0), dict(g=float("nan")),
 ])
 def test_init_rejects_bad_params_before_any_device_call(L, bad):
