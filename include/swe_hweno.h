@@ -134,7 +134,9 @@ int swe_hweno_get_timing(swe_hweno_ctx* ctx, double* ms, long long* launches);
  * (same layouts as above) and only the _f32 calls below plus the type-free ones (sync,
  * destroy, timing, tile); an FP64 call on it, or an _f32 call on an FP64 context, returns
  * SWE_EINVAL. Parameters, alpha and dt stay double on the host; the speeds are reduced in
- * FP32 and dt is formed in FP64 from them.
+ * FP32 and dt is formed in FP64 from them. swe_hweno_init_f32 also rejects eps < 1e-9: the
+ * unnormalised nonlinear weights are of order eps^4 where the data are flat and must stay
+ * normal floats (they overflow for smoothness indicators above about 1e9).
  * ------------------------------------------------------------------------------------------ */
 int swe_hweno_init_f32(const swe_hweno_params* params, const float* b, const float* bx, const float* by,
                        void* stream, swe_hweno_ctx** out);

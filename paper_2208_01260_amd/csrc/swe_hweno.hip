@@ -726,6 +726,8 @@ int init_impl(const swe_hweno_params* p, const T* b, const T* bx, const T* by, v
   if (!out) return SWE_EINVAL;
   *out = nullptr;
   if (!params_ok(p) || !b || !bx || (p->dim == 2 && !by)) return SWE_EINVAL;
+  // single precision: the weights, of order eps^4 where the data are flat, stay normal floats
+  if (sizeof(T) == 4 && !(p->eps >= 1e-9)) return SWE_EINVAL;
   swe_hweno_ctx* c = new (std::nothrow) swe_hweno_ctx();
   if (!c) return SWE_ENOMEM;
   c->p = *p;

@@ -72,6 +72,16 @@ def test_init_rejects_bad_params_before_any_device_call(L, bad):
     assert ctx.value is None
 
 
+def test_init_f32_rejects_eps_below_single_precision_floor(L):
+    """The FP32 weights are of order eps^4 on flat data, so eps < 1e-9 is refused before any
+    device call (eps = 1e-10 is valid for the FP64 context)."""
+    p = _params(eps=1e-10)
+    ctx = ctypes.c_void_p(123)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.swe_hweno_init_f32(ctypes.byref(p), fake, fake, fake, None, ctypes.byref(ctx)) == -1
+    assert ctx.value is None
+
+
 def test_null_arguments_rejected(L):
     p = _params()
     ctx = ctypes.c_void_p()
