@@ -125,8 +125,14 @@ def cpu_baseline(pr, steps):
     oracle.step(ps, sub.state, sub.b, sub.bx, sub.by)
     dt1 = time.perf_counter() - t0
     oracle.set_threads(threads)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": 3.0 * pr.cells * steps / dt, "unit": "cell-RHS/s", "cores": used,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "host_logical_cpus": os.cpu_count(),
             "sample": f"{steps} SSP-RK3 step(s) (3 right-hand sides, limiter, update each) of the same "
                       f"{pr.nx}x{pr.ny} dam-break state, {dt:.1f} s wall on {used} threads",
             "single_thread_value": 3.0 * w * w / dt1,
