@@ -37,21 +37,40 @@ STAGE_BYTES = (27 * 8 + 30 * 8 + 30 * 8) / 3.0  # per node: stage 1 reads 12 wri
 RHS_BYTES = 21 * 8                               # bare right-hand side: read 12, write 9
 
 
-def kernel_source_sha():
-    h = hashlib.sha256()
-    for f in ("hweno_device.hpp", "swe_hweno.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2208_01260_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+def device_code_sha(lib=None):
+    """sha256[:16] of the device code that runs: the .hip_fatbin section (the gfx950 code objects)
+    of the built solver library. Host-only changes to the sources leave it unchanged; any change
+    to a kernel, its inlined routines or its compile flags changes it. None if it cannot be read."""
+    path = lib or os.path.join(ROOT, "paper_2208_01260_amd", "libswe_hweno.so")
+    try:
+        with open(path, "rb") as f:
+            b = f.read()
+    except OSError:
+        return None
+    if b[:4] != b"\x7fELF" or b[4] != 2:
+        return None
+    import struct
+
+    shoff = struct.unpack_from("<Q", b, 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
+    sect = lambda i: struct.unpack_from("<IIQQQQ", b, shoff + i * shentsize)
+    names = sect(shstrndx)[4]
+    for i in range(shnum):
+        nm, _t, _f, _a, off, size = sect(i)
+        if b[names + nm:b.index(b"\0", names + nm)] == b".hip_fatbin":
+            return hashlib.sha256(b[off:off + size]).hexdigest()[:16]
+    return None
 
 
 def measured_traffic(workload):
     """HBM bytes per stage launch from the committed rocprofv3 PMC summary, if it was taken on
-    the current kernel source (else None)."""
+    the device code that runs now (else None)."""
     path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_src_sha") != kernel_source_sha() or d.get("workload") != workload:
+    sha = device_code_sha()
+    if sha is None or d.get("device_code_sha") != sha or d.get("workload") != workload:
         return None
     return d.get("hbm_bytes_per_launch")
 

@@ -551,14 +551,22 @@ bool params_ok(const swe_hweno_params* p) {
   if (p->dim == 1 && p->ny != 1) return false;
   if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 31)) return false;
   if (!(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0))) return false;
+  // finite domain whose node spacing and its reciprocal are finite and positive
+  const auto spacing_ok = [](double a, double b, int n) {
+    const double d = (b - a) / n;
+    return std::isfinite(a) && std::isfinite(b) && d > 0 && std::isfinite(d) && std::isfinite(1.0 / d);
+  };
+  if (!spacing_ok(p->x0, p->x1, p->nx) || (p->dim == 2 && !spacing_ok(p->y0, p->y1, p->ny))) return false;
   // eps >= 1e-20: the kernels form products of two or three weight sums, each at least of
   // order eps^4, and these stay normal doubles down to that floor
   if (!(p->g > 0) || !(p->cfl > 0) || !(p->eps >= 1e-20)) return false;
   if (!std::isfinite(p->g) || !std::isfinite(p->cfl) || !std::isfinite(p->eps)) return false;
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return false;
   if (p->flags & ~(SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER)) return false;
-  if ((p->flags & SWE_FIXED_DT) && !(p->fixed_dt > 0)) return false;
-  if ((p->flags & SWE_FIXED_ALPHA) && (!(p->alpha_x > 0) || (p->dim == 2 && !(p->alpha_y > 0)))) return false;
+  if ((p->flags & SWE_FIXED_DT) && !(p->fixed_dt > 0 && p->fixed_dt <= DBL_MAX)) return false;
+  if ((p->flags & SWE_FIXED_ALPHA) &&
+      (!(p->alpha_x > 0 && p->alpha_x <= DBL_MAX) || (p->dim == 2 && !(p->alpha_y > 0 && p->alpha_y <= DBL_MAX))))
+    return false;
   return true;
 }
 

@@ -60,6 +60,8 @@ def _params(**kw):
     dict(dim=3), dict(nx=3), dict(ny=2), dict(dim=1, ny=4), dict(x1=0.0), dict(y1=-1.0), dict(g=0.0),
     dict(cfl=-1.0), dict(eps=0.0), dict(eps=1e-21), dict(bc_x=2), dict(flags=64), dict(flags=1, fixed_dt=0.0),
     dict(flags=2, alpha_x=1.0, alpha_y=0.0), dict(g=float("nan")),
+    dict(x1=float("inf")), dict(y0=float("-inf")), dict(x0=0.0, x1=1e-320),
+    dict(flags=1, fixed_dt=float("inf")), dict(flags=2, alpha_x=float("inf"), alpha_y=1.0),
 ])
 def test_init_rejects_bad_params_before_any_device_call(L, bad):
     p = _params(**bad)
