@@ -42,8 +42,8 @@ def bottom_slopes_vjp(bxbar, bybar, bbar, domain, bc):
     """bbar += D^T (bxbar, bybar) (in place)."""
     ny, nx = bbar.shape
     p = _params(nx, ny, domain, bc)
-    _lib.check(_lib.lib().swe_hweno_bottom_slopes_vjp(ctypes.byref(p), _dev(bxbar, "bxbar"), _dev(bybar, "bybar"),
-                                                      _dev(bbar, "bbar"),
+    _lib.check(_lib.lib().swe_hweno_bottom_slopes_vjp(ctypes.byref(p), _dev(bxbar, "bxbar", shape=(ny, nx)),
+                                                      _dev(bybar, "bybar", shape=(ny, nx)), _dev(bbar, "bbar"),
                                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
                "swe_hweno_bottom_slopes_vjp")
     return bbar

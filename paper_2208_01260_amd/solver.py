@@ -14,11 +14,15 @@ from . import _lib
 from ._lib import BC_PERIODIC, BC_REFLECTIVE, FIXED_ALPHA, FIXED_DT, NO_LIMITER, SweError  # noqa: F401
 
 
-def _dev(t: torch.Tensor, name: str, dtype=torch.float64) -> int:
+def _dev(t: torch.Tensor, name: str, dtype=torch.float64, shape=None) -> int:
+    """Device pointer of a contiguous CUDA tensor of the given dtype (and shape, when given: the
+    library reads and writes exactly that many elements, so a wrong shape is refused here)."""
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dtype:
         raise TypeError(f"{name} must be a {dtype} CUDA tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}")
     return t.data_ptr()
 
 
@@ -80,7 +84,8 @@ class Solver:
         nd = 6 if self.dim == 2 else 2
         shape = (nd,) + self.shape[1:]
         out = torch.empty(shape, dtype=self.dtype, device=state.device) if out is None else out
-        _lib.check(self._fn["limit"](self._ctx, self._state(state), _dev(out, "out", self.dtype)), "swe_hweno_limit")
+        _lib.check(self._fn["limit"](self._ctx, self._state(state), _dev(out, "out", self.dtype, shape)),
+                   "swe_hweno_limit")
         return out
 
     def alpha(self, state):
@@ -136,7 +141,9 @@ class Solver:
         """(sbar, bbar) = dmbar^T d Lim(state) / d(state, b)."""
         sbar = torch.empty_like(state)
         bb = self._planes()
-        _lib.check(self._L.swe_hweno_limit_vjp(self._ctx, self._state(state), _dev(dmbar, "dmbar"), sbar.data_ptr(),
+        dshape = (6, self.ny, self.nx)
+        _lib.check(self._L.swe_hweno_limit_vjp(self._ctx, self._state(state), _dev(dmbar, "dmbar", shape=dshape),
+                                               sbar.data_ptr(),
                                                bb.data_ptr()), "swe_hweno_limit_vjp")
         return sbar, bb
 
@@ -213,6 +220,9 @@ class Batch:
             if tuple(st.shape) != (9, pr.ny, pr.nx):
                 raise ValueError(f"states[{i}] must have shape {(9, pr.ny, pr.nx)}")
             b, bx, by = t(pr.b), t(pr.bx), t(pr.by)
+            for a, nm in ((b, "b"), (bx, "bx"), (by, "by")):
+                if tuple(a.shape) != (pr.ny, pr.nx):
+                    raise ValueError(f"instance {i}: {nm} must have shape {(pr.ny, pr.nx)}")
             keep += [b, bx, by]
             it = arr[i]
             it.nx, it.ny = pr.nx, pr.ny

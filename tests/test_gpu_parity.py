@@ -228,6 +228,30 @@ def test_lake_at_rest_on_gpu(inputs_mod, torch_cuda, which):
     assert err <= 1e-12
 
 
+def test_binding_refuses_wrongly_shaped_buffers(inputs_mod, torch_cuda):
+    """The library reads and writes exactly the planes its call names, so the binding refuses a
+    buffer of another shape before the call (an undersized one would be accessed out of bounds)."""
+    from paper_2208_01260_amd import adjoint
+
+    torch = torch_cuda
+    pr = inputs_mod.c2_2d(16, "smooth", ny=12)
+    ny, nx = pr.ny, pr.nx
+    f64 = dict(dtype=torch.float64, device="cuda")
+    with solver_for(pr) as s:
+        st = to_dev(torch, pr.state)
+        for bad in ((5, ny, nx), (6, ny, nx - 1)):
+            with pytest.raises(ValueError):
+                s.limit(st, out=torch.empty(bad, **f64))
+            with pytest.raises(ValueError):
+                s.limit_vjp(st, torch.zeros(bad, **f64))
+        with pytest.raises(ValueError):
+            s.rhs(st, out=torch.empty((9, ny, nx + 1), **f64))
+        assert tuple(s.limit(st).shape) == (6, ny, nx)
+    with pytest.raises(ValueError):
+        adjoint.bottom_slopes_vjp(torch.zeros((ny, nx - 1), **f64), torch.zeros((ny, nx), **f64),
+                                  torch.zeros((ny, nx), **f64), pr.domain, pr.bc)
+
+
 def test_determinism(inputs_mod, torch_cuda):
     torch = torch_cuda
     pr = inputs_mod.c3_2d(200, ny=150)
