@@ -693,8 +693,9 @@ int hip_status(hipError_t e) { return e == hipSuccess ? SWE_OK : SWE_EHIP; }
 // Rows marched per wave in 2D: the wave count gx * ceil(ny / rows) should fill whole rounds of
 // the resident-wave slots (one fused-stage wave per SIMD), while each march repays its start-up
 // (four window rows and one extra y-interface, about two rows of work). Cost model: rounds *
-// (rows + 2) over 4 .. 128 rows; ties go to fewer rows. Small grids, which cannot fill the GPU,
-// get short marches and so more wavefronts. SWE_HWENO_ROWS overrides the choice.
+// (rows + 2) over 3 .. 128 rows; ties go to fewer rows. Small grids, which cannot fill the GPU,
+// get short marches and so more wavefronts; below 3 rows the start-up of each wavefront costs
+// more than the extra wavefronts gain. SWE_HWENO_ROWS overrides the choice.
 int choose_rows(int nx, int ny, int slots) {
   if (const char* e = std::getenv("SWE_HWENO_ROWS")) {
     const int r = std::atoi(e);
@@ -703,7 +704,7 @@ int choose_rows(int nx, int ny, int slots) {
   const long gx = (nx + OUT_COLS - 1) / OUT_COLS;
   int best = ROWS_DEFAULT;
   double best_cost = 1e300;
-  for (int r = 4; r <= 128; ++r) {
+  for (int r = 3; r <= 128; ++r) {
     const long waves = gx * ((ny + r - 1) / r);
     const long rounds = (waves + slots - 1) / slots;
     const double cost = (double)rounds * (double)(std::min(r, ny) + 2);
