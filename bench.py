@@ -37,29 +37,68 @@ STAGE_BYTES = (27 * 8 + 30 * 8 + 30 * 8) / 3.0  # per node: stage 1 reads 12 wri
 RHS_BYTES = 21 * 8                               # bare right-hand side: read 12, write 9
 
 
+STAGE_KERNELS = tuple(f"_ZN3swe7k_stageIdLi2ELi{m}EEEvNS_5KArgsIT_EE" for m in range(4))
+
+
+def _elf_sections(b, base=0):
+    """(name, addr, offset, size, link) of each section of the ELF64 image at b[base:]."""
+    import struct
+
+    shoff = struct.unpack_from("<Q", b, base + 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, base + 0x3A)
+    raw = [struct.unpack_from("<IIQQQQII", b, base + shoff + i * shentsize) for i in range(shnum)]
+    names = base + raw[shstrndx][4]
+    return [(b[names + r[0]:b.index(b"\0", names + r[0])].decode(), r[3], base + r[4], r[5], r[6]) for r in raw]
+
+
 def device_code_sha(lib=None):
-    """sha256[:16] of the device code that runs: the .hip_fatbin section (the gfx950 code objects)
-    of the built solver library. Host-only changes to the sources leave it unchanged; any change
-    to a kernel, its inlined routines or its compile flags changes it. None if it cannot be read."""
+    """sha256[:16] of the machine code and kernel descriptors (without their layout-dependent
+    entry offset) of the 2D FP64 stage kernels (k_stage<double, 2, 0..3>) in the gfx950 code
+    object of the built solver library. Host code and other kernels leave it unchanged; any change
+    to these kernels, to the routines they inline or to their compile flags changes it. None if
+    it cannot be read."""
+    import struct
+
     path = lib or os.path.join(ROOT, "paper_2208_01260_amd", "libswe_hweno.so")
     try:
         with open(path, "rb") as f:
             b = f.read()
-    except OSError:
+        fat = next(s for s in _elf_sections(b) if s[0] == ".hip_fatbin")
+        fb = b[fat[2]:fat[2] + fat[3]]
+        magic = b"__CLANG_OFFLOAD_BUNDLE__"
+        if not fb.startswith(magic):
+            return None
+        pos, co = len(magic) + 8, None
+        for _ in range(struct.unpack_from("<Q", fb, len(magic))[0]):
+            off, size, tlen = struct.unpack_from("<QQQ", fb, pos)
+            triple = fb[pos + 24:pos + 24 + tlen].decode()
+            pos += 24 + tlen
+            if triple.endswith("gfx950"):
+                co = fb[off:off + size]
+        if co is None:
+            return None
+        secs = _elf_sections(co)
+        symtab = next(s for s in secs if s[0] == ".symtab")
+        strtab = secs[symtab[4]][2]
+        want = set(STAGE_KERNELS) | {k + ".kd" for k in STAGE_KERNELS}
+        found = {}
+        for i in range(symtab[3] // 24):
+            nm, _info, _other, shndx, value, size = struct.unpack_from("<IBBHQQ", co, symtab[2] + 24 * i)
+            name = co[strtab + nm:co.index(b"\0", strtab + nm)].decode()
+            if name in want:
+                sec = secs[shndx]
+                body = bytearray(co[sec[2] + value - sec[1]:sec[2] + value - sec[1] + size])
+                if name.endswith(".kd"):
+                    body[16:24] = bytes(8)  # kernel_code_entry_byte_offset: moves with the layout
+                found[name] = bytes(body)
+        if set(found) != want:
+            return None
+        h = hashlib.sha256()
+        for name in sorted(found):
+            h.update(name.encode() + b"\0" + found[name])
+        return h.hexdigest()[:16]
+    except (OSError, StopIteration, struct.error, UnicodeDecodeError, ValueError, IndexError):
         return None
-    if b[:4] != b"\x7fELF" or b[4] != 2:
-        return None
-    import struct
-
-    shoff = struct.unpack_from("<Q", b, 0x28)[0]
-    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
-    sect = lambda i: struct.unpack_from("<IIQQQQ", b, shoff + i * shentsize)
-    names = sect(shstrndx)[4]
-    for i in range(shnum):
-        nm, _t, _f, _a, off, size = sect(i)
-        if b[names + nm:b.index(b"\0", names + nm)] == b".hip_fatbin":
-            return hashlib.sha256(b[off:off + size]).hexdigest()[:16]
-    return None
 
 
 def measured_traffic(workload):
