@@ -330,3 +330,149 @@ def test_stored_flop_counts_are_current(oracle_mod):
     # (a one-time handful of constant initialisations may land in either count)
     assert abs(stored["rhs_flops_per_node"] - fresh["rhs_flops_per_node"]) < 0.01
     assert abs(stored["limiter_flops_per_node"] - fresh["limiter_flops_per_node"]) < 0.01
+
+
+# ------------------------------------------------------------------ the 2D limiter in y, alpha and dt
+def _rough2d(nx, ny, domain, bc, seed):
+    """Non-smooth 2D data (a jump in the surface along a slanted line, random momenta of both
+    signs, random derivatives), so that the limiter's nonlinear weights are far from linear and
+    depend on the characteristic decomposition."""
+    rng = np.random.default_rng(seed)
+    x = domain[0] + (np.arange(nx) + 0.5) * (domain[1] - domain[0]) / nx
+    y = domain[2] + (np.arange(ny) + 0.5) * (domain[3] - domain[2]) / ny
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    b = 0.3 * np.exp(-((X - 0.4) ** 2 + (Y - 0.7) ** 2) / 0.05)
+    eta = np.where(X + 0.6 * Y > 0.8, 2.0, 1.4) + 0.05 * rng.normal(size=X.shape)
+    st = np.stack([eta, 0.4 * rng.normal(size=X.shape), 0.4 * rng.normal(size=X.shape)] +
+                  [rng.normal(size=X.shape) for _ in range(6)])
+    return st, b, rng.normal(size=X.shape), rng.normal(size=X.shape)
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (1, 0)])
+def test_limiter_transpose_symmetry_2d(oracle_mod, bc):
+    """x <-> y for the limiter (Sec. 2.2, applied dimension by dimension in Sec. 3): Q^mod of a
+    state is V^mod of the transposed state, with the y-eigenvectors of the node playing the
+    x-eigenvectors' part. Unequal grids and spacings catch a dx/dy or nx/ny mix-up."""
+    O = oracle_mod
+    nx, ny, dom = 23, 17, (0.0, 1.0, 0.0, 1.3)
+    st, b, bx, by = _rough2d(nx, ny, dom, bc, [2208, 7, bc[0], bc[1]])
+    p = O.make_params(2, nx, ny, dom, bc=bc)
+    dm = O.limit(p, st, b, bx, by)
+    assert np.abs(dm - st[3:]).max() > 1e-3  # the limiter acts on this data
+    perm = [0, 2, 1, 6, 8, 7, 3, 5, 4]
+    stT = np.ascontiguousarray(st[perm].transpose(0, 2, 1))
+    pT = O.make_params(2, ny, nx, (dom[2], dom[3], dom[0], dom[1]), bc=(bc[1], bc[0]))
+    dmT = O.limit(pT, stT, b.T.copy(), by.T.copy(), bx.T.copy())
+    dperm = [3, 5, 4, 0, 2, 1]
+    np.testing.assert_allclose(dmT, dm[dperm].transpose(0, 2, 1), rtol=0, atol=1e-13 * np.abs(dm).max())
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_1d_embedding_in_2d_along_y(oracle_mod, inputs_mod, bc):
+    """x-independent 2D data with m = 0, V = 0 and b_x = 0 evolve along y exactly as the 1D scheme
+    does along x (Sec. 2 against Sec. 3): (eta, w, H2, W2, b, b_y) play (eta, m, H, M, b, B). This
+    pins the y-sweep, the y-limiter (y-eigenvectors, y-neighbours, dy) and the y-walls against the
+    1D scheme, which the tables and the convergence tests pin. A jump makes the limiter act."""
+    O, I = oracle_mod, inputs_mod
+    ny, nx = 48, 5
+    y = I.nodes_1d(ny, 0.0, 1.3)
+    rng = np.random.default_rng([2208, 11, bc])
+    b1 = 0.2 * np.cos(2 * np.pi * y / 1.3) + 0.1 * np.sin(4 * np.pi * y / 1.3 + 0.3)
+    B1 = rng.normal(size=ny)
+    st1 = np.stack([np.where((y > 0.4) & (y < 0.8), 2.0, 1.5) + 0.02 * rng.normal(size=ny),
+                    0.3 * rng.normal(size=ny), rng.normal(size=ny), rng.normal(size=ny)])
+    p1 = O.make_params(1, ny, 1, (0.0, 1.3, 0.0, 1.0), bc=(bc, 0))
+    st = np.zeros((9, ny, nx))
+    st[0], st[2], st[6], st[8] = (np.repeat(st1[k][:, None], nx, axis=1) for k in range(4))
+    b = np.repeat(b1[:, None], nx, axis=1)
+    by = np.repeat(B1[:, None], nx, axis=1)
+    p2 = O.make_params(2, nx, ny, (0.0, 0.7, 0.0, 1.3), bc=(0, bc))
+    r1 = O.rhs(p1, st1, b1, B1, alpha_x=3.5)
+    r2 = O.rhs(p2, st, b, np.zeros_like(b), by, 1.0, 3.5)
+    d1 = O.limit(p1, st1, b1, B1)
+    d2 = O.limit(p2, st, b, np.zeros_like(b), by)
+    assert np.abs(d1 - st1[2:]).max() > 1e-3  # the limiter acts on this data
+    for i in range(nx):
+        np.testing.assert_allclose(r2[[0, 2, 6, 8], :, i], r1, rtol=0, atol=1e-14 * np.abs(r1).max())
+        np.testing.assert_allclose(d2[[3, 5], :, i], d1, rtol=0, atol=1e-14 * np.abs(d1).max())
+    assert np.all(r2[[1, 3, 4, 5, 7]] == 0) and np.all(d2[[0, 1, 2, 4]] == 0)
+    s1, _ = O.step(O.make_params(1, ny, 1, (0.0, 1.3, 0.0, 1.0), bc=(bc, 0), flags=O.FIXED_DT, fixed_dt=2e-3),
+                   st1, b1, B1, dt=2e-3)
+    s2, _ = O.step(O.make_params(2, nx, ny, (0.0, 0.7, 0.0, 1.3), bc=(0, bc), flags=O.FIXED_DT, fixed_dt=2e-3),
+                   st, b, np.zeros_like(b), by, dt=2e-3)
+    for i in range(nx):
+        np.testing.assert_allclose(s2[[0, 2, 6, 8], :, i], s1, rtol=0, atol=1e-14 * np.abs(s1).max())
+
+
+def test_limiter_perturbation_is_fourth_order_2d(oracle_mod, inputs_mod):
+    """|V^mod - V| and |Q^mod - Q| = O(dx^4) on the smooth data of Ex. 4.6 (Sec. 2.2 and 3),
+    separately for the x- and the y-limited derivatives."""
+    O, I = oracle_mod, inputs_mod
+    ev, eq = [], []
+    for n in (90, 270):  # (30 -> 90 is pre-asymptotic for the x-derivatives: order 3.2)
+        pr = I.paper_accuracy_2d(n)
+        dm = O.limit(O.params_of(pr), pr.state, pr.b, pr.bx, pr.by)
+        ev.append(np.abs(dm[:3] - pr.state[3:6]).max())
+        eq.append(np.abs(dm[3:] - pr.state[6:9]).max())
+    assert np.log(ev[0] / ev[1]) / np.log(3) > 3.7, ev
+    assert np.log(eq[0] / eq[1]) / np.log(3) > 3.7, eq
+
+
+@pytest.mark.slow
+def test_full_run_fifth_order_2d(oracle_mod, inputs_mod):
+    """Ex. 4.6 data: self-convergence of h, hu, hv over a full run with the limiter at fifth order
+    (Sec. 4, second accuracy example). dt ~ dx^(5/3) and x3 refinement (cell-centred nodes nest).
+    15 -> 45 -> 135 is pre-asymptotic for this data (L-inf orders 2.8-3.8); 45 -> 135 -> 405 gives
+    L1 orders 4.86-5.33 and L-inf 4.58-5.30."""
+    O, I = oracle_mod, inputs_mod
+    S, T = {}, 0.002
+    for n in (45, 135, 405):
+        pr = I.paper_accuracy_2d(n)
+        steps = int(np.ceil(T / (0.3 * pr.dx ** (5.0 / 3.0))))
+        p = O.params_of(pr, flags=O.FIXED_DT, fixed_dt=T / steps)
+        S[n], t, k = O.run(p, pr.state, pr.b, pr.bx, pr.by, nsteps=steps)
+        assert abs(t - T) < 1e-12 and k == steps
+    for f in (0, 1, 2):  # eta - b = h (b is fixed), hu, hv
+        a = S[45][f] - _restrict(S[135])[f]
+        c = S[135][f] - _restrict(S[405])[f]
+        o1 = np.log(np.mean(np.abs(a)) / np.mean(np.abs(c))) / np.log(3)
+        oi = np.log(np.max(np.abs(a)) / np.max(np.abs(c))) / np.log(3)
+        assert o1 > 4.7 and oi > 4.4, (f, o1, oi)
+
+
+def test_alpha_and_dt_golden(oracle_mod):
+    """Hand-computed Lax-Friedrichs speeds and CFL step of two-state data (readings R1 and R11,
+    tests/golden/alpha_dt_two_state.json): the x- and y-maxima are attained at different nodes,
+    so a per-node sum, a wrong sound speed or a swapped spacing gives another step. The
+    right-hand side without given speeds equals the one with the golden speeds."""
+    O = oracle_mod
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alpha_dt_two_state.json")))
+    for case in gold["cases"]:
+        nx, ny, dom = case["nx"], case["ny"], tuple(case["domain"])
+        dim = case["dim"]
+        p = O.make_params(dim, nx, ny, dom, g=case["g"], cfl=case["cfl"])
+        shape = (nx,) if dim == 1 else (ny, nx)
+        left = (np.arange(nx) < case["split"]) if dim == 1 else (np.arange(nx)[None, :] < case["split"]) & np.ones(shape, bool)
+        A, B = case["left"], case["right"]
+        nf = 4 if dim == 1 else 9
+        st = np.zeros((nf,) + shape)
+        st[0] = np.where(left, A["eta"], B["eta"])
+        st[1] = np.where(left, A["m"], B["m"])
+        if dim == 2:
+            st[2] = np.where(left, A["w"], B["w"])
+        b = np.full(shape, case["b"])
+        z = np.zeros(shape)
+        by = z if dim == 2 else None
+        ax, ay = O.alpha(p, st, b, z, by)
+        assert ax == pytest.approx(case["alpha_x"], rel=1e-15, abs=0)
+        if dim == 2:
+            assert ay == pytest.approx(case["alpha_y"], rel=1e-15, abs=0)
+        _, dt = O.step(p, st, b, z, by)
+        assert dt == pytest.approx(case["dt"], rel=2e-16, abs=0)
+        r = O.rhs(p, st, b, z, by)
+        rg = O.rhs(p, st, b, z, by, case["alpha_x"], case.get("alpha_y", 1.0))
+        np.testing.assert_array_equal(r, rg)
+        # the last step of a run is clipped to the final time
+        t_end = 0.4 * case["dt"]
+        _, t, k = O.run(p, st, b, z, by, t_end=t_end)
+        assert k == 1 and t == t_end
