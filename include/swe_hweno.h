@@ -60,7 +60,10 @@ enum { SWE_BC_PERIODIC = 0, SWE_BC_REFLECTIVE = 1 };
 enum {
   SWE_FIXED_DT = 1,     /* every step uses params.fixed_dt instead of the CFL step */
   SWE_FIXED_ALPHA = 2,  /* every right-hand side uses params.alpha_x / alpha_y */
-  SWE_NO_LIMITER = 4    /* skip the derivative limiter (D^mod = D) */
+  SWE_NO_LIMITER = 4,   /* skip the derivative limiter (D^mod = D) */
+  SWE_CHECK_DRY = 8     /* swe_hweno_rhs and swe_hweno_step synchronise and report device-detected
+                           dry or non-finite nodes (as swe_hweno_sync) instead of leaving them to a
+                           later swe_hweno_sync or swe_hweno_run */
 };
 
 typedef struct swe_hweno_ctx swe_hweno_ctx; /* opaque, owned by the library */
@@ -73,21 +76,26 @@ typedef struct {
   double cfl;               /* CFL number, > 0 (the paper uses 0.6, Sec. 4) */
   double eps;               /* epsilon of the nonlinear weights, >= 1e-20 (1e-6, eq. (2.7)) */
   int bc_x, bc_y;           /* SWE_BC_PERIODIC or SWE_BC_REFLECTIVE (mirror about the wall face) */
-  int flags;                /* SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER */
+  int flags;                /* SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER | SWE_CHECK_DRY */
   double fixed_dt;          /* > 0 when SWE_FIXED_DT is set */
   double alpha_x, alpha_y;  /* > 0 when SWE_FIXED_ALPHA is set (alpha_y ignored in 1D) */
 } swe_hweno_params;
 
-/* Create a context: validates params, allocates the stage buffers (about 2.7 states of device
- * memory in 2D), copies the bottom planes b, bx (and by when dim = 2; pass NULL in 1D) from the
- * caller's device memory. stream is a hipStream_t (NULL = the null stream). On error *out is
- * left NULL and nothing is allocated. */
+/* Create a context for the semi-discrete scheme of Sec. 2.1 (1D) or Sec. 3 (2D) on the grid and
+ * parameters of params (g, the CFL number and epsilon as in Sec. 4 and eq. (2.7)): validates
+ * params, allocates the stage buffers (about 2.7 states of device memory in 2D), copies the
+ * bottom planes b, bx (and by when dim = 2; pass NULL in 1D) from the caller's device memory.
+ * stream is a hipStream_t (NULL = the null stream). On error *out is left NULL and nothing is
+ * allocated. */
 int swe_hweno_init(const swe_hweno_params* params, const double* b, const double* bx, const double* by,
                    void* stream, swe_hweno_ctx** out);
 
 /* Right-hand side R(state) of the semi-discrete scheme (eq. (2.8) / (3.8)): rhs has the layout
  * of state. alpha_x < 0 computes alpha from the state on the device (then alpha_y is ignored);
- * otherwise the given alpha_x, alpha_y are used. state and rhs must not overlap. */
+ * otherwise the given alpha_x (and alpha_y in 2D) are used and must be finite and positive
+ * (NaN is SWE_EINVAL). state and rhs must not overlap. A node with h <= 0, or a non-finite
+ * result, sets the context's error flag (reported by swe_hweno_sync, or by this call with
+ * SWE_CHECK_DRY); its right-hand side values are then meaningless. */
 int swe_hweno_rhs(swe_hweno_ctx* ctx, const double* state, double* rhs, double alpha_x, double alpha_y);
 
 /* Limited derivatives Lim(state) (Sec. 2.2, eq. (2.13)): dmod receives 2 planes (H, M) in 1D or
@@ -102,9 +110,10 @@ int swe_hweno_alpha(swe_hweno_ctx* ctx, const double* state, double* alpha_host)
  * SWE_FIXED_DT). If dt_used (HOST pointer) is not NULL the call synchronises and stores the dt. */
 int swe_hweno_step(swe_hweno_ctx* ctx, double* state, double dt, double* dt_used);
 
-/* nsteps steps of state in place, replaying a captured per-step HIP graph. With t_end > 0 it
- * stops at t_end (the last step clipped to it; nsteps <= 0 means "until t_end"); t_out and
- * steps_out (HOST, nullable) receive the time reached and the steps taken. Synchronises. */
+/* nsteps SSP-RK3 steps (eq. (2.11) of Sec. 2.2, each as swe_hweno_step) of state in place,
+ * replaying a captured per-step HIP graph. With t_end > 0 it stops at t_end (the last step
+ * clipped to it; nsteps <= 0 means "until t_end"); t_out and steps_out (HOST, nullable) receive
+ * the time reached and the steps taken. Synchronises and returns device-detected errors. */
 int swe_hweno_run(swe_hweno_ctx* ctx, double* state, int nsteps, double t_end, double* t_out, int* steps_out);
 
 /* Synchronise the context's stream and report (and clear) a device-detected error. */
@@ -154,6 +163,21 @@ int swe_hweno_tile(int* cols_per_wave, int* rows_per_wave);
  * compute-unit count (environment variable SWE_HWENO_ROWS overrides). Host-only. */
 int swe_hweno_ctx_tile(const swe_hweno_ctx* ctx, int* cols_per_wave, int* rows_per_wave);
 
+/* The library's own arithmetic building blocks, applied elementwise on the device for
+ * verification against IEEE division and square root. Each is correctly rounded on its domain:
+ * which = 0: y = 1/x (hardware reciprocal estimate and two Newton steps; 2^-1021 <= |x| <= 2^1021),
+ * 1: y = sqrt(x) (reciprocal square root estimate, one Goldschmidt step and two corrections;
+ * 2^-1000 <= x), 2: y = x/3 (product with the rounded 1/3 and one FMA correction of the exact
+ * remainder; x = 0, returned as +0, or 2^-1000 <= |x|). Outside those domains (where the residuals
+ * are subnormal) the last bit may differ. x and y are DEVICE arrays of n doubles, stream a
+ * hipStream_t; the call synchronises. */
+int swe_hweno_math_check(int which, const double* x, double* y, unsigned long n, void* stream);
+
+/* sha256 (first 16 hex digits) of the sources the library was built from (its HIP sources,
+ * this header and the compiler flags). The Python binding refuses a library whose stamp does
+ * not match the sources beside it. Host-only. */
+const char* swe_hweno_source_hash(void);
+
 /* ------------------------------------------------------------------------------------------
  * Batched solver: many independent 2D instances of uneven sizes, each with its own bottom,
  * state, Lax-Friedrichs speeds and CFL time step, advanced together. Every stage of every
@@ -186,9 +210,11 @@ int swe_hweno_batch_init(const swe_hweno_params* common, const swe_hweno_instanc
 /* nsteps SSP-RK3 steps of every instance (each at its own CFL step; no end time), replayed from
  * captured graphs. Every run starts each instance's clock at 0 and its speeds from its current
  * state; t_out (HOST array of count, nullable) receives the time each instance advanced.
- * Synchronises. An instance whose time step turns non-finite (or whose depth turns
- * non-positive) stops where it is while the others go on, and the call returns SWE_ENONFINITE
- * (SWE_EDRY); nsteps < 1 is SWE_EINVAL. */
+ * Synchronises. An instance whose time step turns non-finite, or whose state is found dry or
+ * non-finite (by the speeds of its initial state or of a stage's result), stops at the start of
+ * the next step while the others go on: its state stays that of the step in which the error was
+ * met (unchanged if its initial state was bad), and the call returns SWE_ENONFINITE (SWE_EDRY).
+ * The error is then cleared: a later run steps the instance again. nsteps < 1 is SWE_EINVAL. */
 int swe_hweno_batch_run(swe_hweno_batch* bt, int nsteps, double* t_out);
 
 /* Rows per wavefront march of the batch kernels (>= 1); swe_hweno_batch_autotune times the

@@ -10,12 +10,11 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# SWE_HWENO_LIB selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("SWE_HWENO_LIB") or os.path.join(HERE, "libswe_hweno.so")
+LIB_PATH = os.path.join(HERE, "libswe_hweno.so")
 
 OK, EINVAL, ENOMEM, EHIP, EDRY, ENONFINITE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_REFLECTIVE = 0, 1
-FIXED_DT, FIXED_ALPHA, NO_LIMITER = 1, 2, 4
+FIXED_DT, FIXED_ALPHA, NO_LIMITER, CHECK_DRY = 1, 2, 4, 8
 ABI_VERSION = 1
 
 # every symbol include/swe_hweno.h declares
@@ -28,7 +27,9 @@ EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alph
            "swe_hweno_init_f32", "swe_hweno_rhs_f32", "swe_hweno_limit_f32", "swe_hweno_alpha_f32",
            "swe_hweno_step_f32", "swe_hweno_run_f32",
            "swe_hweno_rhs_vjp", "swe_hweno_limit_vjp", "swe_hweno_run_vjp", "swe_hweno_bottom_slopes",
-           "swe_hweno_bottom_slopes_vjp", "swe_hweno_run_checkpointed", "swe_hweno_run_vjp_checkpointed")
+           "swe_hweno_bottom_slopes_vjp", "swe_hweno_run_checkpointed", "swe_hweno_run_vjp_checkpointed",
+           "swe_hweno_math_check",
+           "swe_hweno_source_hash")
 
 
 class SweError(RuntimeError):
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_batch_tune_cache_clear": (None, []),
         "swe_hweno_batch_destroy": (None, [vp]),
         "swe_hweno_get_timing": (I, [vp, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
+        "swe_hweno_math_check": (I, [I, dp, dp, ctypes.c_ulong, vp]),
+        "swe_hweno_source_hash": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -111,8 +114,22 @@ def lib() -> ctypes.CDLL:
         fn.argtypes = args
     if L.swe_hweno_abi_version() != ABI_VERSION:
         raise ImportError("libswe_hweno.so ABI version mismatch; rebuild it")
+    check_stamp(L)
     _lib = L
     return L
+
+
+def check_stamp(L) -> str:
+    """The library must have been built from the sources beside it (its stamp is the hash of the
+    HIP sources, the header and the compile flags); a stale build is refused."""
+    from .build import source_hash
+
+    built = L.swe_hweno_source_hash().decode()
+    want = source_hash()
+    if built != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (stamp {built}, sources {want}); "
+                          "rebuild it with __graft_entry__.build()")
+    return built
 
 
 def strerror(code: int) -> str:

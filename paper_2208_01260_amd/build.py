@@ -21,7 +21,27 @@ FLAGS = [
 ]
 
 
+def source_hash(csrc: str = os.path.join(HERE, "csrc"), defines=()) -> str:
+    """sha256 (16 hex digits) of the solver's HIP sources, the C header and the compile flags:
+    the stamp built into libswe_hweno.so and checked by the binding at load."""
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".inc")) and f != "calib.hip")
+    for f in files:
+        h.update(f.encode() + b"\0")
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "swe_hweno.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(FLAGS[:-1] + sorted(defines)).encode())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, out: str = OUT, defines=(), src: str = SRC) -> str:
+    defines = tuple(defines)
+    if src != CALIB_SRC:
+        defines = defines + ('SWE_HWENO_SOURCE_HASH="%s"' % source_hash(os.path.dirname(src), defines),)
     cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + [src, "-o", out + ".tmp"]
     if verbose:
         cmd.append("-Rpass-analysis=kernel-resource-usage")

@@ -343,6 +343,14 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
         } else {
           a.out[q] = R[0]; a.out[n + q] = R[1]; a.out[2 * n + q] = R[3]; a.out[3 * n + q] = R[4];
         }
+        // the node's depth must be positive and the result finite (a product with 0 is NaN
+        // exactly for a non-finite value)
+        const T h = w0[S_ETA] - w0[S_B];
+        T z = T(0.0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) z = fma(R[k], T(0.0), z);
+        if (!(h > T(0.0))) err |= (h == h) ? ERR_DRY : ERR_NONFINITE;
+        if (z != z) err |= ERR_NONFINITE;
       } else {
         // limited derivatives of this stage's state at the node (Sec. 2.2); the x-neighbours'
         // surface, momenta and x-derivatives are the first six slots of their shared fluxes
@@ -400,7 +408,14 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
       for (int k = 0; k < NREC; ++k) { wm1[k] = w0[k]; w0[k] = wp1[k]; wp1[k] = wp2[k]; }
     }
   }
-  if (MODE != MODE_RHS) flush_speeds(a, amx, amy, err);
+  if (MODE != MODE_RHS) {
+    flush_speeds(a, amx, amy, err);
+  } else {
+    int e = err;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, WAVE);
+    if (threadIdx.x == 0 && e) atomicOr(&a.sc->err, e);
+  }
 }
 
 // Workgroups are handed to the 8 XCDs of the device round-robin by linear id. band_tile maps
@@ -453,6 +468,15 @@ __global__ void k_clock(DevScal* s, double t_end) {
 
 __global__ void k_clear_err(DevScal* s) {
   if (threadIdx.x == 0) s->err = 0;
+}
+
+// Elementwise check of the arithmetic building blocks (rcp, sqrt_pos, div3).
+__global__ __launch_bounds__(256) void k_math_check(int which, const double* __restrict__ x, double* __restrict__ y,
+                                                    size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    y[i] = which == 0 ? rcp(v) : (which == 1 ? sqrt_pos(v) : div3(v));
+  }
 }
 
 // Start of a step: alpha of U^n from the previous step's reduction, the CFL step (or fixed),
@@ -562,7 +586,7 @@ bool params_ok(const swe_hweno_params* p) {
   if (!(p->g > 0) || !(p->cfl > 0) || !(p->eps >= 1e-20)) return false;
   if (!std::isfinite(p->g) || !std::isfinite(p->cfl) || !std::isfinite(p->eps)) return false;
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return false;
-  if (p->flags & ~(SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER)) return false;
+  if (p->flags & ~(SWE_FIXED_DT | SWE_FIXED_ALPHA | SWE_NO_LIMITER | SWE_CHECK_DRY)) return false;
   if ((p->flags & SWE_FIXED_DT) && !(p->fixed_dt > 0 && p->fixed_dt <= DBL_MAX)) return false;
   if ((p->flags & SWE_FIXED_ALPHA) &&
       (!(p->alpha_x > 0 && p->alpha_x <= DBL_MAX) || (p->dim == 2 && !(p->alpha_y > 0 && p->alpha_y <= DBL_MAX))))
@@ -793,8 +817,10 @@ int init_impl(const swe_hweno_params* p, const T* b, const T* bx, const T* by, v
 
 template <class T> int rhs_impl(swe_hweno_ctx* c, const T* state, T* rhs, double alpha_x, double alpha_y) {
   if (!c || !state || !rhs || state == rhs || !is_type<T>(c)) return SWE_EINVAL;
-  if (alpha_x >= 0 && (!(alpha_x > 0) || !std::isfinite(alpha_x))) return SWE_EINVAL;
-  if (alpha_x > 0 && c->p.dim == 2 && (!(alpha_y > 0) || !std::isfinite(alpha_y))) return SWE_EINVAL;
+  // alpha_x < 0 asks for the state's speeds; otherwise alpha_x (and alpha_y in 2D) must be
+  // finite and positive (NaN fails every comparison and is refused here)
+  if (!(alpha_x < 0) && !(alpha_x > 0 && std::isfinite(alpha_x))) return SWE_EINVAL;
+  if (alpha_x > 0 && c->p.dim == 2 && !(alpha_y > 0 && std::isfinite(alpha_y))) return SWE_EINVAL;
   const size_t bytes = c->n * c->nf * sizeof(T);
   if ((const char*)rhs < (const char*)state + bytes && (const char*)state < (const char*)rhs + bytes) return SWE_EINVAL;
   if (alpha_x < 0) launch_alpha<T>(c, state, c->sc->a_rhs, c->stream);
@@ -806,7 +832,8 @@ template <class T> int rhs_impl(swe_hweno_ctx* c, const T* state, T* rhs, double
   const int id = time_begin(c, c->stream);
   launch_stage_mode<T, MODE_RHS>(c, a, c->stream);
   time_end(c, id, 0, c->stream);
-  return hip_status(hipGetLastError());
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  return (c->p.flags & SWE_CHECK_DRY) ? take_device_error(c) : SWE_OK;
 }
 
 template <class T> int limit_impl(swe_hweno_ctx* c, const T* state, T* dmod) {
@@ -846,7 +873,7 @@ template <class T> int step_impl(swe_hweno_ctx* c, T* state, double dt, double* 
       return SWE_EHIP;
     return take_device_error(c);
   }
-  return SWE_OK;
+  return (c->p.flags & SWE_CHECK_DRY) ? take_device_error(c) : SWE_OK;
 }
 
 template <class T> int run_impl(swe_hweno_ctx* c, T* state, int nsteps, double t_end, double* t_out, int* steps_out) {
@@ -1005,6 +1032,20 @@ int swe_hweno_get_timing(swe_hweno_ctx* c, double* ms, long long* launches) {
   for (int k = 0; k < 4; ++k) { ms[k] = c->ms[k]; launches[k] = c->launches[k]; }
   return SWE_OK;
 }
+
+int swe_hweno_math_check(int which, const double* x, double* y, unsigned long n, void* stream) {
+  if (which < 0 || which > 2 || !x || !y || n == 0) return SWE_EINVAL;
+  const size_t blocks = (n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 8192 ? blocks : 8192);
+  hipLaunchKernelGGL(k_math_check, dim3(grid), dim3(256), 0, (hipStream_t)stream, which, x, y, (size_t)n);
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  return hip_status(hipStreamSynchronize((hipStream_t)stream));
+}
+
+#ifndef SWE_HWENO_SOURCE_HASH
+#define SWE_HWENO_SOURCE_HASH "unstamped"
+#endif
+const char* swe_hweno_source_hash(void) { return SWE_HWENO_SOURCE_HASH; }
 
 int swe_hweno_sync(swe_hweno_ctx* c) {
   if (!c) return SWE_EINVAL;

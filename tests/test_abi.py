@@ -61,7 +61,7 @@ def _params(**kw):
     dict(cfl=-1.0), dict(eps=0.0), dict(eps=1e-21), dict(bc_x=2), dict(flags=64), dict(flags=1, fixed_dt=0.0),
     dict(flags=2, alpha_x=1.0, alpha_y=0.0), dict(g=float("nan")),
     dict(x1=float("inf")), dict(y0=float("-inf")), dict(x0=0.0, x1=1e-320),
-    dict(flags=1, fixed_dt=float("inf")), dict(flags=2, alpha_x=float("inf"), alpha_y=1.0),
+    dict(flags=1, fixed_dt=float("inf")), dict(flags=2, alpha_x=float("inf"), alpha_y=1.0), dict(flags=16),
 ])
 def test_init_rejects_bad_params_before_any_device_call(L, bad):
     p = _params(**bad)
@@ -122,6 +122,26 @@ def test_null_arguments_rejected(L):
     assert L.swe_hweno_run_vjp_checkpointed(None, 1, 1, None, None, None, None, None) == -1
     assert L.swe_hweno_bottom_slopes(None, None, None, None, None) == -1
     assert L.swe_hweno_bottom_slopes_vjp(None, None, None, None, None) == -1
+
+
+def test_stale_library_is_refused(L, monkeypatch):
+    """The binding checks the library's source stamp against the sources beside it: a library
+    built from other sources fails to load (no silent use of a stale build)."""
+    from paper_2208_01260_amd import _lib, build
+
+    assert _lib.check_stamp(L) == build.source_hash()
+    monkeypatch.setattr(build, "source_hash", lambda *a, **k: "0000000000000000")
+    with pytest.raises(ImportError):
+        _lib.check_stamp(L)
+
+
+def test_math_check_validates_on_the_host(L):
+    fake = ctypes.c_void_p(0x1000)
+    assert L.swe_hweno_math_check(3, fake, fake, 4, None) == -1
+    assert L.swe_hweno_math_check(-1, fake, fake, 4, None) == -1
+    assert L.swe_hweno_math_check(0, None, fake, 4, None) == -1
+    assert L.swe_hweno_math_check(0, fake, None, 4, None) == -1
+    assert L.swe_hweno_math_check(0, fake, fake, 0, None) == -1
 
 
 def test_batch_init_rejects_bad_arguments(L):

@@ -186,4 +186,7 @@ def test_batch_dry_instance_reported_others_advance(inputs_mod, torch_cuda):
             bt.run(2)
         for i in (0, 2):
             assert np.array_equal(bt.states[i].cpu().numpy(), plain_run(torch, probs[i], 2)[0]), i
+        # the dry node is met by the speeds of the initial state, before the first step: the
+        # instance is stopped by that step's prologue and keeps its state unchanged
+        assert np.array_equal(bt.states[1].cpu().numpy(), bad)
         bt.sync()  # the error was reported and cleared
