@@ -136,6 +136,25 @@ int swe_hweno_abi_version(void);
 int swe_hweno_set_timing(swe_hweno_ctx* ctx, int on);
 int swe_hweno_get_timing(swe_hweno_ctx* ctx, double* ms, long long* launches);
 
+/* One SSP-RK3 step (as swe_hweno_step) with no context and no device allocation. For callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The stage buffers and device scalars live in one static
+ * device array of swe_hweno_noalloc_capacity() bytes (32 MiB), one copy per GPU, held by the
+ * library until the process ends. A grid needs 256 bytes plus 24 planes (2D) or 10 planes (1D)
+ * of nx*ny doubles; a larger grid is rejected with SWE_EINVAL (2D: at most 174,761 nodes, e.g.
+ * 418 x 418). params, state, dt and dt_used as for swe_hweno_init and swe_hweno_step (FP64);
+ * b, bx and by (NULL in 1D) are read in place, not copied, and must stay valid until the stream
+ * (a hipStream_t, NULL = the null stream) reaches the step. The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine) and, with dt_used == NULL, does not
+ * synchronise. Every call on one GPU uses that GPU's single array and overwrites what the
+ * previous call left: calls that overlap on one GPU (several streams or host threads) race
+ * and must be serialised by the caller. Device-detected errors are reported only through a
+ * non-NULL dt_used (the call then synchronises). */
+int swe_hweno_step_noalloc(const swe_hweno_params* params, double* state, const double* b, const double* bx,
+                           const double* by, double dt, void* stream, double* dt_used);
+/* Bytes of the static device array behind swe_hweno_step_noalloc. Host-only, no HIP call. */
+unsigned long swe_hweno_noalloc_capacity(void);
+
 /* ------------------------------------------------------------------------------------------
  * Single precision. The same scheme, kernels and launch shapes with every array and all device
  * arithmetic in FP32 (the paper's lake-at-rest tables report single, double and quadruple

@@ -28,7 +28,7 @@ EXPORTS = ("swe_hweno_init", "swe_hweno_rhs", "swe_hweno_limit", "swe_hweno_alph
            "swe_hweno_step_f32", "swe_hweno_run_f32",
            "swe_hweno_rhs_vjp", "swe_hweno_limit_vjp", "swe_hweno_run_vjp", "swe_hweno_bottom_slopes",
            "swe_hweno_bottom_slopes_vjp", "swe_hweno_run_checkpointed", "swe_hweno_run_vjp_checkpointed",
-           "swe_hweno_math_check",
+           "swe_hweno_step_noalloc", "swe_hweno_noalloc_capacity", "swe_hweno_math_check",
            "swe_hweno_source_hash")
 
 
@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
         "swe_hweno_batch_tune_cache_clear": (None, []),
         "swe_hweno_batch_destroy": (None, [vp]),
         "swe_hweno_get_timing": (I, [vp, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
+        "swe_hweno_step_noalloc": (I, [P, dp, dp, dp, dp, D, vp, ctypes.POINTER(D)]),
+        "swe_hweno_noalloc_capacity": (ctypes.c_ulong, []),
         "swe_hweno_math_check": (I, [I, dp, dp, ctypes.c_ulong, vp]),
         "swe_hweno_source_hash": (ctypes.c_char_p, []),
     }

@@ -479,6 +479,24 @@ __global__ __launch_bounds__(256) void k_math_check(int which, const double* __r
   }
 }
 
+// Allocation-free step (swe_hweno_step_noalloc): its stage buffers and device scalars live in
+// this array, one copy per GPU, held until the process ends. Host code takes its address with
+// hipGetSymbolAddress (per device) and never uses the array's name as a device address.
+constexpr size_t NOALLOC_BYTES = size_t(32) << 20;
+constexpr size_t NOALLOC_SCAL = 256;  // DevScal at the start, stage planes after it
+static_assert(sizeof(DevScal) <= NOALLOC_SCAL, "device scalars must fit their slot");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Start of an allocation-free step: the fixed speeds and a cleared error flag (the array keeps
+// whatever the previous call on this GPU left).
+__global__ void k_noalloc_setup(DevScal* s, unsigned long long afx, unsigned long long afy) {
+  if (threadIdx.x == 0) {
+    s->a_fix[0] = afx;
+    s->a_fix[1] = afy;
+    s->err = 0;
+  }
+}
+
 // Start of a step: alpha of U^n from the previous step's reduction, the CFL step (or fixed),
 // clipped at t_end; clears the reductions this step fills.
 __global__ void k_prologue(DevScal* s, int dim, int fixed_dt, double fdt, double cfl, double dx, double dy,
@@ -928,6 +946,76 @@ template <class T> int run_impl(swe_hweno_ctx* c, T* state, int nsteps, double t
   return e;
 }
 
+// Device address of `scratch` on the current device, looked up once per device.
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SWE_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SWE_EHIP;
+    it = g_scratch_addr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return SWE_OK;
+}
+
+// Bytes of scratch an allocation-free step needs: device scalars, then S1, S2 (nf planes each)
+// and D^{n,mod} (nd planes).
+size_t noalloc_bytes(const swe_hweno_params* p) {
+  const size_t n = (size_t)p->nx * (size_t)(p->dim == 2 ? p->ny : 1);
+  const size_t planes = p->dim == 2 ? 2 * 9 + 6 : 2 * 4 + 2;
+  return NOALLOC_SCAL + planes * n * sizeof(double);
+}
+
+int step_noalloc_impl(const swe_hweno_params* p, double* state, const double* b, const double* bx,
+                      const double* by, double dt, void* stream, double* dt_used) {
+  if (!params_ok(p) || !state || !b || !bx || (p->dim == 2 && !by)) return SWE_EINVAL;
+  if (!(dt <= DBL_MAX)) return SWE_EINVAL;
+  if (noalloc_bytes(p) > NOALLOC_BYTES) return SWE_EINVAL;
+  void* base = nullptr;
+  if (const int e = scratch_address(&base)) return e;
+  // a context on the host stack that points into the scratch array and at the caller's bottom
+  swe_hweno_ctx c;
+  c.p = *p;
+  c.stream = (hipStream_t)stream;
+  c.nf = p->dim == 2 ? 9 : 4;
+  c.nd = p->dim == 2 ? 6 : 2;
+  c.n = (size_t)p->nx * (size_t)(p->dim == 2 ? p->ny : 1);
+  c.b = (void*)b;
+  c.bx = (void*)bx;
+  c.by = (void*)by;
+  c.sc = (DevScal*)base;
+  double* planes = (double*)((char*)base + NOALLOC_SCAL);
+  c.S1 = planes;
+  c.S2 = planes + (size_t)c.nf * c.n;
+  c.Dn = planes + (size_t)2 * c.nf * c.n;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || cus <= 0)
+      cus = 256;
+    c.rows = choose_rows(p->nx, p->dim == 2 ? p->ny : 1, 4 * cus);
+  }
+  if (dt > 0) { c.p.flags |= SWE_FIXED_DT; c.p.fixed_dt = dt; }
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(64), 0, c.stream, c.sc, dbits(p->alpha_x),
+                     dbits(p->dim == 2 ? p->alpha_y : 0.0));
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, c.stream, c.sc, 0.0);
+  launch_alpha<double>(&c, state, c.sc->a_next, c.stream);
+  enqueue_step<double>(&c, state, 0, c.stream);
+  if (hipGetLastError() != hipSuccess) return SWE_EHIP;
+  if (dt_used) {
+    if (hipMemcpyAsync(dt_used, &c.sc->dt, sizeof(double), hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return SWE_EHIP;
+    return take_device_error(&c);
+  }
+  return SWE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1032,6 +1120,13 @@ int swe_hweno_get_timing(swe_hweno_ctx* c, double* ms, long long* launches) {
   for (int k = 0; k < 4; ++k) { ms[k] = c->ms[k]; launches[k] = c->launches[k]; }
   return SWE_OK;
 }
+
+int swe_hweno_step_noalloc(const swe_hweno_params* params, double* state, const double* b, const double* bx,
+                           const double* by, double dt, void* stream, double* dt_used) {
+  return step_noalloc_impl(params, state, b, bx, by, dt, stream, dt_used);
+}
+
+unsigned long swe_hweno_noalloc_capacity(void) { return (unsigned long)NOALLOC_BYTES; }
 
 int swe_hweno_math_check(int which, const double* x, double* y, unsigned long n, void* stream) {
   if (which < 0 || which > 2 || !x || !y || n == 0) return SWE_EINVAL;

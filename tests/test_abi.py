@@ -144,6 +144,24 @@ def test_math_check_validates_on_the_host(L):
     assert L.swe_hweno_math_check(0, fake, fake, 0, None) == -1
 
 
+def test_noalloc_step_validates_on_the_host(L):
+    """The allocation-free step checks its arguments and the size of its static array before any
+    device call: null pointers, bad parameters and grids whose stage buffers exceed the array."""
+    cap = L.swe_hweno_noalloc_capacity()
+    assert cap == 32 << 20
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ok = _params(nx=418, ny=418)
+    assert 256 + 24 * 418 * 418 * 8 <= cap
+    for p, args in ((None, (fake, fake, fake, fake)), (ok, (None, fake, fake, fake)), (ok, (fake, None, fake, fake)),
+                    (ok, (fake, fake, None, fake)), (ok, (fake, fake, fake, None)),
+                    (_params(nx=419, ny=418), (fake, fake, fake, fake)), (_params(dim=3), (fake, fake, fake, fake)),
+                    (_params(dim=1, ny=1, nx=419431), (fake, fake, fake, None))):
+        pp = ctypes.byref(p) if p is not None else None
+        assert L.swe_hweno_step_noalloc(pp, *args, 0.0, None, None) == -1
+    assert L.swe_hweno_step_noalloc(ctypes.byref(ok), fake, fake, fake, fake, float("nan"), None, None) == -1
+    assert L.swe_hweno_step_noalloc(ctypes.byref(ok), fake, fake, fake, fake, float("inf"), None, None) == -1
+
+
 def test_batch_init_rejects_bad_arguments(L):
     from paper_2208_01260_amd import _lib
 
@@ -179,5 +197,6 @@ def test_calibration_library_loads_and_checks_arguments():
     L = calib._load()
     t, m = ctypes.c_double(), ctypes.c_double()
     assert L.swe_calib_fp64_fma(3, 0.5, ctypes.byref(t), ctypes.byref(m)) == -1
+    assert L.swe_calib_fp64_fma(16, 0.5, ctypes.byref(t), ctypes.byref(m)) == -1
     assert L.swe_calib_fp64_fma(2, 0.0, ctypes.byref(t), ctypes.byref(m)) == -1
     assert L.swe_calib_fp64_fma(2, 0.5, None, ctypes.byref(m)) == -1
