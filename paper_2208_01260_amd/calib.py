@@ -22,7 +22,8 @@ def _load():
 
 
 def fp64_fma_ceiling(waves_per_simd=2, seconds=0.5):
-    """(TFLOP/s, shader MHz) of a sustained FP64 FMA stream on the current device."""
+    """(TFLOP/s, shader MHz) of a sustained FP64 FMA stream on the current device with
+    waves_per_simd (1, 2, 4 or 8) wavefronts per SIMD, eight independent chains each."""
     t, m = ctypes.c_double(), ctypes.c_double()
     rc = _load().swe_calib_fp64_fma(int(waves_per_simd), float(seconds), ctypes.byref(t), ctypes.byref(m))
     if rc != 0:

@@ -10,12 +10,14 @@
 
 namespace swe_calib {
 
-constexpr int CHAINS = 4;   // independent FMA chains per lane
+constexpr int CHAINS = 8;   // independent FMA chains per lane
 constexpr int UNROLL = 16;  // FMAs per chain per loop trip
 
-// Each lane runs CHAINS independent FMA chains; lane 0 of each block records its shader-clock
-// and constant-rate clock spans. Dynamic LDS only limits how many blocks share a CU.
-__global__ __launch_bounds__(64) void k_fma_stream(double* out, unsigned long long* spans, int iters, double b,
+// Each lane runs CHAINS independent FMA chains; lane 0 of each wavefront records its shader-clock
+// and constant-rate clock spans. A block is four wavefronts, which the device places on the four
+// SIMDs of a CU; dynamic LDS limits how many blocks share a CU, so W blocks per CU are W
+// wavefronts per SIMD.
+__global__ __launch_bounds__(256) void k_fma_stream(double* out, unsigned long long* spans, int iters, double b,
                                                    double c) {
   extern __shared__ double pad[];
   const int t = threadIdx.x;
@@ -24,7 +26,7 @@ __global__ __launch_bounds__(64) void k_fma_stream(double* out, unsigned long lo
   __syncthreads();
   double a[CHAINS];
 #pragma unroll
-  for (int j = 0; j < CHAINS; ++j) a[j] = pad[(t + j) & 63] * 1e-3 + j;
+  for (int j = 0; j < CHAINS; ++j) a[j] = pad[(t + j) & 255] * 1e-3 + j;
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
@@ -35,11 +37,12 @@ __global__ __launch_bounds__(64) void k_fma_stream(double* out, unsigned long lo
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < CHAINS; ++j) s += a[j];
-  out[(size_t)blockIdx.x * 64 + t] = s;
+  out[(size_t)blockIdx.x * 256 + t] = s;
   const unsigned long long c1 = clock64(), w1 = wall_clock64();
-  if (t == 0) {
-    spans[2 * (size_t)blockIdx.x] = c1 - c0;
-    spans[2 * (size_t)blockIdx.x + 1] = w1 - w0;
+  if ((t & 63) == 0) {
+    const size_t wv = (size_t)blockIdx.x * 4 + (t >> 6);
+    spans[2 * wv] = c1 - c0;
+    spans[2 * wv + 1] = w1 - w0;
   }
 }
 
@@ -47,13 +50,15 @@ __global__ __launch_bounds__(64) void k_fma_stream(double* out, unsigned long lo
 
 extern "C" {
 
-// Sustained FP64 FMA rate with waves_per_simd (1 or 2) one-wavefront blocks per SIMD, launched
-// back to back for about `seconds` on the current device and default stream. Reports (host
+// Sustained FP64 FMA rate with waves_per_simd (1, 2, 4 or 8) wavefronts per SIMD (that many
+// four-wavefront blocks per CU), launched back to back for about `seconds` on the current device
+// and default stream. Reports (host
 // pointers) the median TFLOP/s of the second half of the launches (FMA = 2 flops) and the mean
 // shader clock of those launches in MHz. Returns 0, -1 for bad arguments, -3 for a HIP error.
 // Synchronises the device; allocates and frees its own buffers.
 int swe_calib_fp64_fma(int waves_per_simd, double seconds, double* tflops, double* shader_mhz) {
-  if ((waves_per_simd != 1 && waves_per_simd != 2) || !(seconds > 0.0) || seconds > 60.0 || !tflops || !shader_mhz)
+  if ((waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4 && waves_per_simd != 8) ||
+      !(seconds > 0.0) || seconds > 60.0 || !tflops || !shader_mhz)
     return -1;
   int dev = 0, cus = 0, wclk_khz = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -3;
@@ -67,29 +72,35 @@ int swe_calib_fp64_fma(int waves_per_simd, double seconds, double* tflops, doubl
       return -3;
     lds_cu = (size_t)v;
   }
-  // blocks per CU = 4 SIMDs x waves_per_simd: LDS per block just above 1/(that+1) of the CU's
-  const int per_cu = 4 * waves_per_simd;
+  // blocks per CU = waves_per_simd: LDS per block just above 1/(that+1) of the CU's
+  const int per_cu = waves_per_simd;
   const size_t lds = ((lds_cu / per_cu) / 512) * 512 - 1024;
   if (lds * (per_cu + 1) <= lds_cu || lds * per_cu > lds_cu) return -1;
+  {
+    int blk = 0;  // the device's largest LDS allocation per block
+    if (hipDeviceGetAttribute(&blk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return -3;
+    if (lds > (size_t)blk) return -1;
+  }
   const int nblk = cus * per_cu * 4;  // four rounds of resident blocks per launch
+  const int nwave = nblk * 4;
   const int iters = 1 << 11;
   double* out = nullptr;
   unsigned long long* spans = nullptr;
-  if (hipMalloc(&out, sizeof(double) * 64 * (size_t)nblk) != hipSuccess) return -3;
-  if (hipMalloc(&spans, sizeof(unsigned long long) * 2 * (size_t)nblk) != hipSuccess) {
+  if (hipMalloc(&out, sizeof(double) * 256 * (size_t)nblk) != hipSuccess) return -3;
+  if (hipMalloc(&spans, sizeof(unsigned long long) * 2 * (size_t)nwave) != hipSuccess) {
     (void)hipFree(out);
     return -3;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = 0;
   std::vector<double> rate, mhz;
-  std::vector<unsigned long long> h(2 * (size_t)nblk);
-  const double flops = 2.0 * swe_calib::CHAINS * swe_calib::UNROLL * (double)iters * 64.0 * nblk;
+  std::vector<unsigned long long> h(2 * (size_t)nwave);
+  const double flops = 2.0 * swe_calib::CHAINS * swe_calib::UNROLL * (double)iters * 256.0 * nblk;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = -3;
   const auto t0 = std::chrono::steady_clock::now();
   while (rc == 0) {
     if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = -3; break; }
-    hipLaunchKernelGGL(swe_calib::k_fma_stream, dim3(nblk), dim3(64), lds, 0, out, spans, iters, 0.999999, 1e-7);
+    hipLaunchKernelGGL(swe_calib::k_fma_stream, dim3(nblk), dim3(256), lds, 0, out, spans, iters, 0.999999, 1e-7);
     if (hipGetLastError() != hipSuccess || hipEventRecord(e1, nullptr) != hipSuccess ||
         hipEventSynchronize(e1) != hipSuccess) { rc = -3; break; }
     float ms = 0.f;
@@ -99,7 +110,7 @@ int swe_calib_fp64_fma(int waves_per_simd, double seconds, double* tflops, doubl
       break;
     }
     double cyc = 0.0, wt = 0.0;
-    for (int i = 0; i < nblk; ++i) { cyc += (double)h[2 * i]; wt += (double)h[2 * i + 1]; }
+    for (int i = 0; i < nwave; ++i) { cyc += (double)h[2 * i]; wt += (double)h[2 * i + 1]; }
     rate.push_back(flops / (ms * 1e-3) / 1e12);
     mhz.push_back(wt > 0 ? cyc / wt * wclk_khz * 1e-3 : 0.0);
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
