@@ -126,3 +126,53 @@ def test_single_precision_functions(oracle_mod, inputs_mod):
     d32, _, _ = O.run_delta("f32", p, pr.state, pr.b, pr.bx, pr.by, nsteps=5)
     s0 = pr.state.astype(np.float32).astype(np.float64)
     assert np.abs((s32 - s0) - d32).max() <= 1e-6 * np.abs(d32).max()
+
+
+@pytest.mark.slow
+def test_c5_central_difference_epsilon_sweep(oracle_mod, inputs_mod):
+    """On the adjoint workload (256^2, 100 steps at a fixed dt with frozen speeds, gauge misfit
+    loss ~7e-11), the central difference of the loss along a smooth unit bottom direction
+    approaches the oracle's forward-mode tangent at second order from large steps (truncation
+    branch) and departs from it again below about 1e-4 (rounding branch: the loss's own rounding
+    divided by the step). So a quotient at step 1e-6 is limited by the loss's rounding, not by the
+    derivative it is compared with; at the best step the two agree to ~1e-10 (Sec. 4's workloads
+    have no adjoint; the scheme differentiated is that of eq. (2.11) with readings R1, R22)."""
+    O, I = oracle_mod, inputs_mod
+    pr = I.c5_adjoint(256)
+    nsteps = 100
+    ax, ay = O.alpha(O.params_of(pr), pr.state, pr.b, pr.bx, pr.by)
+    al = (1.1 * ax, 1.1 * ay)
+    dt = 0.6 / (al[0] / pr.dx + al[1] / pr.dy)
+    p = O.params_of(pr, flags=O.FIXED_DT | O.FIXED_ALPHA, fixed_dt=dt, alpha_x=(al[0],) * 3, alpha_y=(al[1],) * 3)
+    g = pr.extra["gauges"]
+    bt = pr.b + pr.extra["target_db"]
+    tgt, _, _ = O.run(p, pr.state, bt, pr.bx + pr.extra["target_dbx"], pr.by + pr.extra["target_dby"], nsteps=nsteps)
+    htgt = tgt[0][g[:, 0], g[:, 1]] - bt[g[:, 0], g[:, 1]]
+    X, Y = I.nodes_2d(pr.nx, pr.ny, pr.domain)
+    rng = np.random.default_rng(16)
+    db, dbx, dby = np.zeros_like(X), np.zeros_like(X), np.zeros_like(X)
+    for _ in range(4):  # a smooth direction with its analytic slopes
+        cx, cy, w, a = rng.uniform(0.3, 1.7), rng.uniform(0.3, 1.7), rng.uniform(0.08, 0.2), rng.standard_normal()
+        e = a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * w * w))
+        db += e
+        dbx += -e * (X - cx) / (w * w)
+        dby += -e * (Y - cy) / (w * w)
+    nrm = np.sqrt(np.sum(db ** 2))
+    db, dbx, dby = db / nrm, dbx / nrm, dby / nrm
+
+    def loss(c):
+        s, _, _ = O.run(p, pr.state, pr.b + c * db, pr.bx + c * dbx, pr.by + c * dby, nsteps=nsteps)
+        h = s[0][g[:, 0], g[:, 1]] - (pr.b + c * db)[g[:, 0], g[:, 1]]
+        return float(np.sum((h - htgt) ** 2))
+
+    sT, dT = O.run_jvp(p, pr.state, np.zeros_like(pr.state), pr.b, pr.bx, pr.by, db, dbx, dby, nsteps)
+    h = sT[0][g[:, 0], g[:, 1]] - pr.b[g[:, 0], g[:, 1]]
+    dh = dT[0][g[:, 0], g[:, 1]] - db[g[:, 0], g[:, 1]]
+    tangent = float(np.sum(2.0 * (h - htgt) * dh))
+    err = {}
+    for e in (1e-2, 1e-4, 1e-6, 1e-8):
+        err[e] = abs((loss(e) - loss(-e)) / (2 * e) - tangent) / abs(tangent)
+    print("central difference vs tangent:", {f"{k:.0e}": f"{v:.2e}" for k, v in err.items()})
+    assert err[1e-4] <= 1e-8                              # the derivative itself
+    assert err[1e-2] >= 5 * err[1e-4]                     # truncation branch above
+    assert err[1e-6] >= 10 * err[1e-4] and err[1e-8] >= 10 * err[1e-6]  # rounding branch below
