@@ -237,8 +237,10 @@ int swe_hweno_batch_init(const swe_hweno_params* common, const swe_hweno_instanc
 int swe_hweno_batch_run(swe_hweno_batch* bt, int nsteps, double* t_out);
 
 /* Rows per wavefront march of the batch kernels (>= 1); swe_hweno_batch_autotune times the
- * fused kernel on the batch's own data for a set of candidates (into scratch buffers, the
- * states are not touched), keeps the fastest and returns it. The choice is cached for the life
+ * first two fused stage kernels of a step (limiter as configured) on the batch's own data for a
+ * set of candidates (8 to 64 rows; they write only the batch's stage buffers, the states are not
+ * touched), keeps the fastest and returns it. Rows per march are the tile's one free dimension:
+ * its width is the 60 output columns of a 64-lane wavefront. The choice is cached for the life
  * of the process per size class: the device's architecture and compute-unit count and
  * power-of-two buckets of the instance count, the total nodes and the largest instance width
  * and height. A batch of a class already tuned takes the cached rows without timing. The cache
