@@ -98,27 +98,55 @@ __device__ __forceinline__ int fold(int i, int n, int bc, bool& refl) {
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// A global pointer the compiler cannot see through. Fields are reached by bumping such a pointer
+// by the field stride, so that the only loop-invariant scalar is the stride itself: without it the
+// compiler keeps one hoisted 64-bit base per (array, field), about thirty scalar pairs, and spills
+// them to vector-register lanes that are read back on every row.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* opq(T* p) {
+  auto g = (__attribute__((address_space(1))) T*)p;
+  asm("" : "+v"(g));
+  return g;
+}
+
 // Raw node record at (i, j) in the slots of hweno_device.hpp, ghost values by parity:
 // across an x-wall m, H1, W1, M2, B1 are odd; across a y-wall w, W1, H2, M2, B2 are odd.
 template <int DIM, class T>
-__device__ __forceinline__ void load_rec(const KArgs<T>& a, const T* __restrict__ S, int i, int j, T r[NREC]) {
-  bool rx, ry = false;
+__device__ __forceinline__ void load_raw(const KArgs<T>& a, const T* __restrict__ S, int i, int j, T r[NREC],
+                                         bool& rx, bool& ry) {
+  ry = false;
   const int ii = fold(i, a.nx, a.bcx, rx);
   const int jj = DIM == 2 ? fold(j, a.ny, a.bcy, ry) : 0;
   const size_t n = (size_t)a.nx * (DIM == 2 ? a.ny : 1);
   const size_t q = (size_t)jj * a.nx + ii;
   if (DIM == 2) {
+    auto p = opq(S + q);
 #pragma unroll
-    for (int f = 0; f < 9; ++f) r[f] = S[f * n + q];
-    r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = a.by[q];
+    for (int f = 0; f < 9; ++f) {
+      r[f] = *p;
+      if (f < 8) p = opq(p + n);
+    }
+    r[S_B] = *opq(a.b + q); r[S_BX] = *opq(a.bx + q); r[S_BY] = *opq(a.by + q);
   } else {
     r[S_ETA] = S[q]; r[S_M] = S[n + q]; r[S_W] = T(0.0);
     r[S_H1] = S[2 * n + q]; r[S_M1] = S[3 * n + q]; r[S_W1] = T(0.0);
     r[S_H2] = T(0.0); r[S_M2] = T(0.0); r[S_W2] = T(0.0);
     r[S_B] = a.b[q]; r[S_BX] = a.bx[q]; r[S_BY] = T(0.0);
   }
+}
+
+// The ghost parities of a record read across an x-wall (rx) or a y-wall (ry).
+template <class T>
+__device__ __forceinline__ void apply_flips(T r[NREC], bool rx, bool ry) {
   if (rx) { r[S_M] = -r[S_M]; r[S_H1] = -r[S_H1]; r[S_W1] = -r[S_W1]; r[S_M2] = -r[S_M2]; r[S_BX] = -r[S_BX]; }
   if (ry) { r[S_W] = -r[S_W]; r[S_W1] = -r[S_W1]; r[S_H2] = -r[S_H2]; r[S_M2] = -r[S_M2]; r[S_BY] = -r[S_BY]; }
+}
+
+template <int DIM, class T>
+__device__ __forceinline__ void load_rec(const KArgs<T>& a, const T* __restrict__ S, int i, int j, T r[NREC]) {
+  bool rx, ry;
+  load_raw<DIM>(a, S, i, j, r, rx, ry);
+  apply_flips(r, rx, ry);
 }
 
 // Node fluxes through LDS: slot k of a NodeF at lane l is sn[k][l].
@@ -282,15 +310,20 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
 
   for (int r = r0; r < r1; ++r) {
     const size_t q = (size_t)r * a.nx + cq;
-    // loads whose latency the x-sweep hides: the next row of the window, U^n and D^{n,mod}
+    // loads whose latency the x-sweep hides: the next row of the window, U^n and D^{n,mod}. The new
+    // row's ghost parities are applied where the y-sweep first reads it, so that no instruction
+    // before that point depends on these loads.
     T wp2[NREC];
-    if (DIM == 2) load_rec<DIM>(a, a.S, c, r + 2, wp2);
+    bool f2x = false, f2y = false;
+    if (DIM == 2) load_raw<DIM>(a, a.S, c, r + 2, wp2, f2x, f2y);
     T un_[3], dn_[6];
     if (MODE == MODE_STAGE1 || MODE == MODE_STAGE2) {
+      auto pS = opq(a.Sn + q);
+      auto pD = opq(a.Dn + q);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) if (k < nu) un_[k] = a.Sn[k * n + q];
+      for (int k = 0; k < 3; ++k) if (k < nu) { un_[k] = *pS; pS = opq(pS + n); }
 #pragma unroll
-      for (int k = 0; k < 6; ++k) if (k < nd) dn_[k] = a.Dn[k * n + q];
+      for (int k = 0; k < 6; ++k) if (k < nd) { dn_[k] = *pD; pD = opq(pD + n); }
     }
     T R[9];
 #pragma unroll
@@ -323,6 +356,7 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
     // y-sweep: interface r+1/2 from rows r-1 .. r+2
     if (DIM == 2) {
       IfO<T> o;
+      apply_flips(wp2, f2x, f2y);
       yring_store(syf, r + 2, lane, wp2, a.g);
       auto fy = [&](int k, NodeF<T>& X) {
         yring_load(syf, r - 1 + k, lane, k == 0 ? wm1 : (k == 1 ? w0 : (k == 2 ? wp1 : wp2)), X);
@@ -338,8 +372,12 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
     if (col_out) {
       if (MODE == MODE_RHS) {
         if (DIM == 2) {
+          auto po = opq(a.out + q);
 #pragma unroll
-          for (int k = 0; k < 9; ++k) a.out[k * n + q] = R[k];
+          for (int k = 0; k < 9; ++k) {
+            *po = R[k];
+            if (k < 8) po = opq(po + n);
+          }
         } else {
           a.out[q] = R[0]; a.out[n + q] = R[1]; a.out[2 * n + q] = R[3]; a.out[3 * n + q] = R[4];
         }
@@ -370,6 +408,8 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           Dm[0] = w0[S_H1]; Dm[1] = w0[S_M1]; Dm[2] = w0[S_W1];
           Dm[3] = w0[S_H2]; Dm[4] = w0[S_M2]; Dm[5] = w0[S_W2];
         }
+        auto po = opq(a.out + q);
+        auto pdo = opq(MODE == MODE_STAGE0 ? a.Dn_out + q : a.out + q);
         // SSP-RK3 combination (eq. (2.11)), written over a common denominator
         const int uslot[3] = {S_ETA, S_M, S_W};
         const int rd[6] = {3, 4, 5, 6, 7, 8};
@@ -383,7 +423,8 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           else if (MODE == MODE_STAGE1) v = (T(3.0) * un_[k] + u) * T(0.25);
           else v = div3(un_[k] + T(2.0) * u);
           Unew[k] = v;
-          a.out[k * n + q] = v;
+          *po = v;
+          po = opq(po + n);
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -392,13 +433,15 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           T v;
           if (MODE == MODE_STAGE0) {
             v = u;
-            a.Dn_out[k * n + q] = Dm[k];
+            *pdo = Dm[k];
+            pdo = opq(pdo + n);
           } else if (MODE == MODE_STAGE1) {
             v = (T(3.0) * dn_[k] + u) * T(0.25);
           } else {
             v = div3(dn_[k] + T(2.0) * u);
           }
-          a.out[(nu + k) * n + q] = v;
+          *po = v;
+          po = opq(po + n);
         }
         speeds(Unew[0], Unew[1], Unew[2], w0[S_B], a.g, amx, amy, err);
       }
