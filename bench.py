@@ -166,6 +166,77 @@ def device_ceilings(torch, dev):
             "copy_GBs": copy_gbs, "copy_frac_of_hbm_peak": copy_gbs / 8000.0}
 
 
+def _sysfs_board():
+    """The first GPU's board power (hwmon, microwatts) and current shader-clock level files."""
+    import glob
+
+    pw = sorted(glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*/power1_average") +
+                glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*/power1_input"))
+    clk = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+    return (pw[0] if pw else None), (clk[0] if clk else None)
+
+
+def board_state(torch, s, st, seconds=2.0):
+    """Board power and shader clock while the fused stage kernels run back to back (graph replays
+    of 20 steps for about `seconds`), sampled from sysfs every 50 ms, beside the idle board just
+    before. The MI355X's FP64 peak assumes its 2.4 GHz maximum shader clock; a kernel that holds
+    the board at its power limit runs at a lower clock."""
+    import re
+    import statistics
+    import threading
+
+    pw, clk = _sysfs_board()
+    if pw is None and clk is None:
+        return None
+    samples, phase, stop = [], ["idle"], [False]
+
+    def read():
+        rec = {"phase": phase[0]}
+        try:
+            rec["w"] = int(open(pw).read()) / 1e6 if pw else None
+        except (OSError, ValueError):
+            rec["w"] = None
+        try:
+            cur = [l for l in open(clk).read().splitlines() if l.rstrip().endswith("*")] if clk else []
+            m = re.search(r"(\d+)\s*Mhz", cur[0], re.I) if cur else None
+            rec["mhz"] = int(m.group(1)) if m else None
+        except OSError:
+            rec["mhz"] = None
+        return rec
+
+    def loop():
+        while not stop[0]:
+            samples.append(read())
+            time.sleep(0.05)
+
+    th = threading.Thread(target=loop, daemon=True)
+    th.start()
+    time.sleep(0.5)
+    phase[0] = "stage"
+    t0, steps = time.perf_counter(), 0
+    while time.perf_counter() - t0 < seconds:
+        s.run(st, nsteps=20)
+        torch.cuda.synchronize()
+        steps += 20
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    stop[0] = True
+    th.join()
+
+    def med(ph, key):
+        v = [r[key] for r in samples if r["phase"] == ph and r.get(key) is not None]
+        if ph == "stage":
+            v = v[4:]  # the first 200 ms: power and clock still settling
+        return statistics.median(v) if v else None
+
+    out = {"source": {"power": pw, "clock": clk}, "stage_steps": steps, "stage_ms_per_step": ms_per_step,
+           "idle_board_w": med("idle", "w"), "stage_board_w": med("stage", "w"),
+           "idle_shader_mhz": med("idle", "mhz"), "stage_shader_mhz": med("stage", "mhz"),
+           "samples": len(samples)}
+    print(f"[bench] board while the stage kernels run: {out['stage_board_w']} W at {out['stage_shader_mhz']} MHz "
+          f"(idle {out['idle_board_w']} W)", file=sys.stderr, flush=True)
+    return out
+
+
 def flop_counts():
     """Algorithmic flops per node (right-hand side, limiter), counted by the oracle's
     operation-counting scalar and stored by tests/golden/make_flop_counts.py."""
@@ -364,6 +435,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-loop", type=int, default=64, help="instances timed one by one for comparison")
+    ap.add_argument("--no-power", action="store_true", help="skip the board power / clock sample")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the measured device ceilings (FP64 FMA stream, device copy)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -489,6 +561,13 @@ def main():
                     "stage_code_sha": device_code_sha()},
         "cell_steps_per_s": cells * args.steps / wall,
     }
+    if not args.no_power:
+        board = board_state(torch, s, st)
+        if board is not None:
+            line["board"] = board
+            if board.get("stage_shader_mhz"):
+                # the same kernel time against the peak at the clock the board sustained
+                roof["frac_at_sustained_clock"] = achieved / (PEAK_FP64 * board["stage_shader_mhz"] / 2400.0)
     s.close()
     if not args.no_ceilings:
         line["device_ceilings"] = device_ceilings(torch, dev)
