@@ -369,8 +369,8 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
       assemble<1>(yprev, ynew, eta, H1, H2, a.g, a.idy, R);
     }
 
-    if (col_out) {
-      if (MODE == MODE_RHS) {
+    if (MODE == MODE_RHS) {
+      if (col_out) {
         if (DIM == 2) {
           auto po = opq(a.out + q);
 #pragma unroll
@@ -389,9 +389,14 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
         for (int k = 0; k < 9; ++k) z = fma(R[k], T(0.0), z);
         if (!(h > T(0.0))) err |= (h == h) ? ERR_DRY : ERR_NONFINITE;
         if (z != z) err |= ERR_NONFINITE;
-      } else {
+      }
+    } else if (MODE != MODE_STAGE1 || col_out) {
         // limited derivatives of this stage's state at the node (Sec. 2.2); the x-neighbours'
-        // surface, momenta and x-derivatives are the first six slots of their shared fluxes
+        // surface, momenta and x-derivatives are the first six slots of their shared fluxes.
+        // The first and third stages run the limiter and the update on every lane and mask only
+        // the stores and the speed reduction, which leaves the compiler free to schedule them
+        // across the row; the second stage keeps them under the branch (each form is the faster
+        // one for its stage on this device; the results are the same bits either way).
         T Dm[6];
         if (a.limiter) {
           limit_frame(w0[S_ETA], w0[S_M], w0[S_W], w0[S_B], sn[0][lb], sn[1][lb], sn[2][lb], sn[0][ld], sn[1][ld],
@@ -408,12 +413,11 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           Dm[0] = w0[S_H1]; Dm[1] = w0[S_M1]; Dm[2] = w0[S_W1];
           Dm[3] = w0[S_H2]; Dm[4] = w0[S_M2]; Dm[5] = w0[S_W2];
         }
-        auto po = opq(a.out + q);
-        auto pdo = opq(MODE == MODE_STAGE0 ? a.Dn_out + q : a.out + q);
         // SSP-RK3 combination (eq. (2.11)), written over a common denominator
         const int uslot[3] = {S_ETA, S_M, S_W};
         const int rd[6] = {3, 4, 5, 6, 7, 8};
         T Unew[3] = {T(0.0), T(0.0), T(0.0)};
+        T vout[9];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (k >= nu) break;
@@ -423,8 +427,7 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           else if (MODE == MODE_STAGE1) v = (T(3.0) * un_[k] + u) * T(0.25);
           else v = div3(un_[k] + T(2.0) * u);
           Unew[k] = v;
-          *po = v;
-          po = opq(po + n);
+          vout[k] = v;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -433,18 +436,33 @@ __device__ __forceinline__ void stage_tile(const KArgs<T>& a, int tx, int ty) {
           T v;
           if (MODE == MODE_STAGE0) {
             v = u;
-            *pdo = Dm[k];
-            pdo = opq(pdo + n);
           } else if (MODE == MODE_STAGE1) {
             v = (T(3.0) * dn_[k] + u) * T(0.25);
           } else {
             v = div3(dn_[k] + T(2.0) * u);
           }
-          *po = v;
-          po = opq(po + n);
+          vout[nu + k] = v;
         }
-        speeds(Unew[0], Unew[1], Unew[2], w0[S_B], a.g, amx, amy, err);
-      }
+        // only the interior columns store and reduce their speeds
+        if (col_out) {
+          auto po = opq(a.out + q);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            if (k >= nu + nd) break;
+            *po = vout[k];
+            po = opq(po + n);
+          }
+          if (MODE == MODE_STAGE0) {
+            auto pdo = opq(a.Dn_out + q);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              if (k >= nd) break;
+              *pdo = Dm[k];
+              pdo = opq(pdo + n);
+            }
+          }
+          speeds(Unew[0], Unew[1], Unew[2], w0[S_B], a.g, amx, amy, err);
+        }
     }
     if (DIM == 2) {
 #pragma unroll
