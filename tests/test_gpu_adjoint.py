@@ -56,6 +56,10 @@ def cases(I):
         ("acc2d_40_periodic", I.paper_accuracy_2d(40)),
         ("c3_45x38_dam", I.c3_2d(45, ny=38)),
         ("c2s_37x29", I.c2_2d(37, "smooth", ny=29)),
+        # wider than one 64-interface workgroup per row: sums of neighbouring workgroups meet,
+        # across a periodic wrap and at ragged row ends
+        ("acc2d_100_periodic", I.paper_accuracy_2d(100)),
+        ("c3_130x67_dam", I.c3_2d(130, ny=67)),
     ]
 
 
